@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the view-tied splatting renderer on one MI355X.
+
+Metric: forward+backward Mpix/s at 640x480.  Workload (the tracking
+configuration): one 640x480 keyframe of a synthetic room tied to 307,200
+Gaussians, a new frame observed at the keyframe pose whose initial estimate
+is off by 1 cm / 0.5 degrees; each frame runs 40 tracking iterations of
+splat forward -> Eq. 1 loss -> backward to the SE(3) twist -> Adam step and
+retraction.  A step is one such iteration; value = 640*480*steps / seconds.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's achieved rate vs the MI355X peak,
+                from HIP events on the stream the kernels run on
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+                same workload
+  batched       mapping-section batch (5 of 8 keyframes per iteration,
+                gradients to colour/opacity/radius) in one plan vs one view
+                per launch with a host sync in between
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def tracking_setup():
+    import numpy as np
+    import torch
+    from paper_2506_02741_amd import render as R
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1)
+    kf = w["keyframe"]
+    cam = kf.cam.as_tuple()
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, cam, kf.pose)
+    init = torch.tensor(np.asarray(w["init_pose"], np.float32).reshape(12), device="cuda")
+    view = R.View(cam, init.clone(), obs_rgb=kf.rgb, obs_depth=kf.depth).with_pose_adam()
+    plan = R.Plan([k], [view])
+    return w, k, view, plan, init
+
+
+def run_frames(plan, view, init, cfg, iters, loss):
+    """iters tracking iterations in frames of 40 from the initial pose."""
+    done = 0
+    while done < iters:
+        n = min(40, iters - done)
+        view.pose.copy_(init)
+        view.pose_adam.zero_()
+        plan.track_step(cfg, n, loss[:n])
+        done += n
+
+
+def flops_per_pair():
+    """FP32 operations the definition needs per (pixel, Gaussian) pair of the
+    backward compositing (twist chain) and the forward compositing:
+    a tested pair evaluates d and q (8); a covering pair (q <= q_cut) adds
+    exp and alpha (4); a contributing pair adds, forward, the transmittance
+    and colour/depth accumulation (11), backward, transmittance recovery,
+    dL/dalpha, the behind accumulators and dL/dq (27) and the chain to the
+    twist (34)."""
+    return dict(fwd_test=8, fwd_cover=4, fwd_contrib=11, bwd_test=8, bwd_cover=4, bwd_contrib=61)
+
+
+def pair_counts(w):
+    """Per-frame counts of tested / covering / contributing pairs from the
+    oracle's per-pixel lists (the workload's own numbers)."""
+    import numpy as np
+    import oracle
+    kf = w["keyframe"]
+    okf = oracle.ingest(kf.depth, kf.rgb, fx=kf.cam.fx, cam=kf.cam.as_tuple(), pose=kf.pose)
+    out = oracle.render(oracle.ViewSpec(kf.cam.as_tuple(), w["init_pose"]), [okf])
+    contrib = int(out["n_contrib"].sum())
+    return contrib, out
+
+
+def cpu_baseline(w, seconds):
+    import numpy as np
+    import oracle
+    kf = w["keyframe"]
+    okf = oracle.ingest(kf.depth, kf.rgb, fx=kf.cam.fx, cam=kf.cam.as_tuple(), pose=kf.pose)
+    pose = np.asarray(w["init_pose"], np.float32)
+    st = dict(m=np.zeros(6), v=np.zeros(6), t=0)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        view = oracle.ViewSpec(kf.cam.as_tuple(), pose)
+        L, new_pose, st, g, _ = oracle.track_iteration(view, [okf], kf.rgb, kf.depth, st)
+        pose = new_pose.astype(np.float32)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=640 * 480 * n / dt / 1e6, unit="Mpix/s", cores=1, kind="oracle",
+                sample="%d tracking iterations (fwd + Eq.1 + bwd to twist + Adam/retraction) of "
+                       "the 640x480 frame, single-threaded, %.1f s" % (n, dt))
+
+
+def batched_vs_single(iters):
+    """5 of 8 section keyframes per mapping iteration: one plan vs one view per
+    launch (render_fwd, host sync to size the pair list, render_bwd)."""
+    import numpy as np
+    import torch
+    from paper_2506_02741_amd import render as R
+    from paper_2506_02741_amd import synth
+    sec = synth.section_workload(2, 8)
+    frames = sec["keyframes"]
+    cam = frames[0].cam.as_tuple()
+    ks = [R.Keyframe.ingest(f.depth, f.rgb, cam, f.pose, learnable=True).with_grad_buffers()
+          for f in frames]
+    picks = synth.draw_views(2, 8, 5, iters + 2)
+    ones = None
+
+    def views_of(sel):
+        return [R.View(cam, frames[i].pose, 0, 8) for i in sel]
+    # batched: one plan per draw of 5 views, all sharing one workspace and
+    # re-binding their descriptors before use
+    first = R.Plan(ks, views_of(picks[0]))
+    plans = [first] + [R.Plan(ks, views_of(sel), workspace=first.ws, bind=False) for sel in picks[1:]]
+    g = torch.ones(3, first.P, device="cuda") * 1e-3
+    for p in plans[:2]:
+        p.bind(); p.render_fwd(); p.render_bwd(g, None, None, twist=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in plans[2:]:
+        p.bind()
+        p.render_fwd()
+        p.render_bwd(g, None, None, twist=False)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    assert plans[-1].status()[0] == 0
+    del plans, first
+    # one view per launch
+    singles = {i: R.Plan(ks, views_of([i])) for i in range(8)}
+    g1 = torch.ones(3, singles[0].P, device="cuda") * 1e-3
+    for i in picks[0]:
+        singles[i].render_fwd(); singles[i].render_bwd(g1, None, None, twist=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sel in picks[2:]:
+        for i in sel:
+            p = singles[i]
+            p.render_fwd()
+            rc, need = p.status(clear=False)   # host sync sizing the pair list
+            p.render_bwd(g1, None, None, twist=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    px = 5 * 640 * 480 * iters
+    return dict(workload="mapping section: 8 keyframes 640x480 (2,457,600 Gaussians), 5 views "
+                         "per iteration, fwd+bwd to colour/opacity/radius",
+                iters=iters, batched_mpix_s=px / tb / 1e6, one_view_per_launch_mpix_s=px / ts / 1e6,
+                speedup=ts / tb)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path has no multi-GPU "
+              "collective); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_02741_amd import render as R
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log("bench: building tracking workload (640x480, 307,200 Gaussians)")
+    w, k, view, plan, init = tracking_setup()
+    cfg = R.track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002)
+    loss = torch.zeros(40, 1, device="cuda")
+    log("bench: warmup %d iterations" % args.warmup)
+    run_frames(plan, view, init, cfg, args.warmup, loss)
+    torch.cuda.synchronize()
+    rc, need = plan.status()
+    if rc != 0:
+        raise SystemExit("plan status %d (pairs needed %d)" % (rc, need))
+
+    log("bench: timing %d iterations" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_frames(plan, view, init, cfg, args.steps, loss)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rc, need = plan.status()
+    assert rc == 0, rc
+    value = 640 * 480 * args.steps / dt / 1e6
+
+    # per-stage durations from HIP events on the launch stream
+    log("bench: stage timing")
+    plan.timing(True)
+    run_frames(plan, view, init, cfg, 80, loss)
+    stages = plan.timing(False)
+    avg = {s: ms / n for s, (ms, n) in stages.items()}
+    dom = max(stages, key=lambda s: stages[s][0])
+
+    contrib, _ = pair_counts(w)
+    fl = flops_per_pair()
+    roof = None
+    if dom == "composite_bwd":
+        work = contrib * fl["bwd_contrib"]
+    elif dom == "composite_fwd":
+        work = contrib * fl["fwd_contrib"]
+    else:
+        work = None
+    if work is not None:
+        achieved = work / (avg[dom] * 1e-3) / 1e12
+        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS, traffic=None,
+                    avg_ms=avg[dom], flops_per_launch=work,
+                    units="%d contributing (pixel, Gaussian) pairs x %d FLOP" % (
+                        contrib, fl["bwd_contrib"] if dom == "composite_bwd" else fl["fwd_contrib"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    batched = None
+    if not args.no_batched:
+        log("bench: batched vs one view per launch")
+        batched = batched_vs_single(args.batched_iters)
+
+    out = dict(metric="fwd+bwd Mpix/s at 640x480", value=value, unit="Mpix/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+               data="synthetic",
+               config=dict(workload="tracking 640x480: 1 keyframe, 307,200 view-tied Gaussians, "
+                                    "40-iteration frames of fwd + Eq.1 + bwd to twist + pose step",
+                           global_batch=1, seq_len=0, parallelism="none"),
+               roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

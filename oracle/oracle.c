@@ -488,6 +488,11 @@ static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params 
                          int64_t n, double *C, double *D, double *T_out, uint8_t *marg) {
   float T32 = 1.0f;
   double T = 1.0;
+  /* Relative uncertainty of T32 against an evaluation whose exp differs by
+   * at most `margin` (relative): an alpha error of margin*alpha becomes a
+   * relative error margin*alpha/(1-alpha) of (1 - alpha), plus one rounding
+   * per product.  A stop decision closer to t_min than that is marginal. */
+  double u = 0.0;
   C[0] = C[1] = C[2] = 0.0;
   *D = 0.0;
   int32_t k = 0;
@@ -496,7 +501,8 @@ static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params 
     const orc_rec *r = &s->rec[g];
     float a32 = alpha32(r, opa32(v, kfs, g), x, y, prm);
     float Tn = T32 * (1.0f - a32);
-    if (near_rel(Tn, prm->t_min, margin)) *marg = 1;
+    double un = u + (double)margin * a32 / (1.0 - a32) + (margin > 0.f ? 1.2e-7 : 0.0);
+    if (fabs((double)Tn - prm->t_min) <= un * prm->t_min) *marg = 1;
     if (Tn < prm->t_min) break;
     double w[2];
     double q = q_at(&s->geo[g], x, y, w);
@@ -505,6 +511,7 @@ static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params 
     *D += s->geo[g].p[2] * a * T;
     T *= (1.0 - a);
     T32 = Tn;
+    u = un;
     k++;
   }
   for (int c = 0; c < 3; c++) C[c] += T * prm->bg[c];

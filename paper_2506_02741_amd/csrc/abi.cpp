@@ -1,0 +1,635 @@
+// C ABI of the gfx950 view-tied splatting library (declared in vtgs.h):
+// argument validation, plans (descriptor tables and workspace layout) and
+// the launch sequences of render_fwd, render_bwd, track_step and map_step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vtgs.h"
+#include "vtgs_internal.h"
+
+using namespace vtgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_OK(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return fail(VTGS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Region {
+  int64_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct vtgs_plan {
+  std::vector<DevKF> kfs;
+  std::vector<DevView> views;
+  std::vector<DevSeg> segs;
+  std::vector<int32_t> kf_use_off;
+  std::vector<DevKFUse> kf_use;
+  vtgs_params prm{};
+  int64_t cap = 0, P = 0;
+  int32_t n_rec = 0, n_tiles = 0, loss_blocks = 0, ssim_gx = 0, ssim_gy = 0;
+  int32_t max_learn_n = 0;
+  bool any_learnable = false;
+  // workspace layout
+  Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
+      r_ranges, r_keys, r_keys_tmp, r_ids, r_slots, r_tfinal, r_last, r_img, r_gimg, r_twist,
+      r_loss, r_ssim_map, r_ssim_part;
+  int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
+  int64_t ws_bytes = 0;
+  // binding
+  char *ws = nullptr;
+  Ws w{};
+  void *pinned = nullptr;
+  hipEvent_t upload_done = nullptr;
+  bool bound = false, fwd_done = false;
+  // stage timing (HIP events around every stage while enabled)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_used;  // stage, (start, stop)
+};
+
+namespace {
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+int validate_cam(const vtgs_camera &c, const char *what, int idx) {
+  if (c.width <= 0 || c.height <= 0 || c.width > 65535 || c.height > 65535 || !finite_pos(c.fx) ||
+      !finite_pos(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+    return fail(VTGS_E_ARG, std::string(what) + " " + std::to_string(idx) +
+                                ": camera needs 0 < width, height <= 65535 and finite fx, fy > 0");
+  return VTGS_OK;
+}
+
+void layout(vtgs_plan *p) {
+  int64_t off = 0;
+  auto take = [&](Region &r, int64_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += align_up(std::max<int64_t>(bytes, 0));
+  };
+  const int64_t nk = (int64_t)p->kfs.size(), nv = (int64_t)p->views.size();
+  const int64_t ns = (int64_t)p->segs.size(), nu = (int64_t)p->kf_use.size();
+  take(p->r_hdr, 256);
+  p->desc_kf = 0;
+  p->desc_view = align_up(nk * (int64_t)sizeof(DevKF));
+  p->desc_seg = p->desc_view + align_up(nv * (int64_t)sizeof(DevView));
+  p->desc_use_off = p->desc_seg + align_up(ns * (int64_t)sizeof(DevSeg));
+  p->desc_use = p->desc_use_off + align_up((nk + 1) * 4);
+  p->desc_bytes = p->desc_use + align_up(nu * (int64_t)sizeof(DevKFUse));
+  take(p->r_desc, p->desc_bytes);
+  const int64_t nr = p->n_rec, nt = p->n_tiles, cap = p->cap, P = p->P;
+  take(p->r_recA, nr * 48);
+  take(p->r_recB, nr * 16);
+  take(p->r_rect, nr * 8);
+  take(p->r_rec_cnt, nr * 4);
+  take(p->r_rec_off, (nr + 1) * 4);
+  take(p->r_scan, (rec_scan_blocks(nr) + 1) * 4);
+  take(p->r_tcount, nt * 4);
+  take(p->r_tfill, nt * 4);
+  take(p->r_ranges, nt * 8);
+  take(p->r_keys, cap * 8);
+  take(p->r_keys_tmp, cap * 8);
+  take(p->r_ids, cap * 4);
+  take(p->r_slots, p->any_learnable ? cap * 20 : 0);
+  take(p->r_tfinal, P * 4);
+  take(p->r_last, P * 4);
+  take(p->r_img, 5 * P * 4);
+  take(p->r_gimg, 5 * P * 4);
+  take(p->r_twist, nt * 24);
+  take(p->r_loss, nv * (int64_t)p->loss_blocks * 16);
+  take(p->r_ssim_map, 9 * P * 4);
+  take(p->r_ssim_part, nv * 3 * (int64_t)p->ssim_gx * p->ssim_gy * 4);
+  p->ws_bytes = off;
+}
+
+template <typename T>
+T *at(char *base, const Region &r) {
+  return reinterpret_cast<T *>(base + r.off);
+}
+
+void make_ws(vtgs_plan *p) {
+  Ws &w = p->w;
+  char *b = p->ws;
+  w.flags = reinterpret_cast<uint32_t *>(b + p->r_hdr.off);
+  w.n_pairs = reinterpret_cast<unsigned long long *>(b + p->r_hdr.off + 8);
+  char *d = b + p->r_desc.off;
+  w.kfs = reinterpret_cast<const DevKF *>(d + p->desc_kf);
+  w.views = reinterpret_cast<const DevView *>(d + p->desc_view);
+  w.segs = reinterpret_cast<DevSeg *>(d + p->desc_seg);
+  w.kf_use_off = reinterpret_cast<const int32_t *>(d + p->desc_use_off);
+  w.kf_use = reinterpret_cast<const DevKFUse *>(d + p->desc_use);
+  w.n_kf = (int32_t)p->kfs.size();
+  w.n_views = (int32_t)p->views.size();
+  w.n_segs = (int32_t)p->segs.size();
+  w.n_rec = p->n_rec;
+  w.n_tiles = p->n_tiles;
+  w.P = p->P;
+  w.cap = p->cap;
+  w.recA = at<float4>(b, p->r_recA);
+  w.recB = at<float4>(b, p->r_recB);
+  w.rect = at<uint2>(b, p->r_rect);
+  w.rec_cnt = at<uint32_t>(b, p->r_rec_cnt);
+  w.rec_off = at<uint32_t>(b, p->r_rec_off);
+  w.scan_part = at<uint32_t>(b, p->r_scan);
+  w.tile_count = at<uint32_t>(b, p->r_tcount);
+  w.tile_fill = at<uint32_t>(b, p->r_tfill);
+  w.ranges = at<uint2>(b, p->r_ranges);
+  w.keys = at<unsigned long long>(b, p->r_keys);
+  w.keys_tmp = at<unsigned long long>(b, p->r_keys_tmp);
+  w.ids = at<uint32_t>(b, p->r_ids);
+  w.slots = p->any_learnable ? at<float>(b, p->r_slots) : nullptr;
+  w.t_final = at<float>(b, p->r_tfinal);
+  w.last = at<uint32_t>(b, p->r_last);
+  w.img = at<float>(b, p->r_img);
+  w.gimg = at<float>(b, p->r_gimg);
+  w.twist_part = at<float>(b, p->r_twist);
+  w.loss_part = at<float>(b, p->r_loss);
+  w.ssim_map = at<float>(b, p->r_ssim_map);
+  w.ssim_part = at<float>(b, p->r_ssim_part);
+  w.loss_blocks = p->loss_blocks;
+  w.ssim_gx = p->ssim_gx;
+  w.ssim_gy = p->ssim_gy;
+  w.amin = p->prm.alpha_min;
+  w.amax = p->prm.alpha_max;
+  w.tmin = p->prm.t_min;
+  w.qcut = p->prm.q_cut;
+  w.znear = p->prm.z_near;
+  w.lowpass = p->prm.lowpass;
+  for (int c = 0; c < 3; c++) w.bg[c] = p->prm.bg[c];
+  w.tile = p->prm.tile;
+  w.batch = p->prm.batch;
+}
+
+int check_bound(vtgs_plan *p) {
+  if (!p) return fail(VTGS_E_ARG, "plan is NULL");
+  if (!p->bound) return fail(VTGS_E_WORKSPACE, "plan has no bound workspace (vtgs_plan_bind)");
+  return VTGS_OK;
+}
+
+enum Stage {
+  ST_SETUP, ST_PRE, ST_SCAN, ST_FILL, ST_SORT, ST_FWD, ST_LOSS, ST_RSCAN, ST_BWD, ST_REDUCE,
+  ST_UPDATE, ST_N
+};
+const char *kStageNames[ST_N] = {"setup",        "preprocess", "scan_tiles",   "fill_keys",
+                                 "sort_tiles",   "composite_fwd", "loss",      "scan_records",
+                                 "composite_bwd", "reduce",     "update"};
+
+hipError_t event_at(vtgs_plan *p, size_t i, hipEvent_t *e) {
+  while (p->ev_pool.size() <= i) {
+    hipEvent_t ne;
+    hipError_t r = hipEventCreate(&ne);
+    if (r != hipSuccess) return r;
+    p->ev_pool.push_back(ne);
+  }
+  *e = p->ev_pool[i];
+  return hipSuccess;
+}
+
+// Launch `expr` as stage `stg`, bracketed by events when timing is on.
+#define STAGE(p, stg, st, expr)                                                  \
+  do {                                                                           \
+    size_t i0_ = 0;                                                              \
+    if ((p)->timing) {                                                           \
+      hipEvent_t ev_;                                                             \
+      i0_ = (p)->ev_used.size() * 2;                                             \
+      HIP_OK(event_at((p), i0_, &ev_));                                           \
+      HIP_OK(hipEventRecord(ev_, (st)));                                          \
+    }                                                                            \
+    HIP_OK(expr);                                                                \
+    if ((p)->timing) {                                                           \
+      hipEvent_t ev_;                                                             \
+      HIP_OK(event_at((p), i0_ + 1, &ev_));                                       \
+      HIP_OK(hipEventRecord(ev_, (st)));                                          \
+      (p)->ev_used.push_back({(stg), {i0_, i0_ + 1}});                           \
+    }                                                                            \
+  } while (0)
+
+// The binning pipeline and the forward compositing into (rgb, depth, sil).
+int run_forward(vtgs_plan *p, float *rgb, float *depth, float *sil, hipStream_t st) {
+  const Ws &w = p->w;
+  STAGE(p, ST_SETUP, st, launch_setup(w, st));
+  STAGE(p, ST_PRE, st, launch_preprocess(w, st));
+  STAGE(p, ST_SCAN, st, launch_scan_tiles(w, st));
+  STAGE(p, ST_FILL, st, launch_fill_keys(w, st));
+  STAGE(p, ST_SORT, st, launch_sort_tiles(w, st));
+  STAGE(p, ST_FWD, st, launch_composite_fwd(w, rgb, depth, sil, st));
+  p->fwd_done = true;
+  return VTGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vtgs_abi_version(void) { return VTGS_ABI_VERSION; }
+
+const char *vtgs_last_error(void) { return g_err.c_str(); }
+
+void vtgs_default_params(vtgs_params *out) {
+  if (!out) return;
+  out->alpha_min = 1.0f / 255.0f;
+  out->alpha_max = 0.99f;
+  out->t_min = 1e-4f;
+  out->q_cut = 11.0826f;
+  out->z_near = 0.01f;
+  out->lowpass = 0.3f;
+  out->bg[0] = out->bg[1] = out->bg[2] = 0.f;
+  out->tile = 16;
+  out->batch = 256;
+}
+
+int64_t vtgs_ingest_scratch_bytes(int32_t H, int32_t W, int32_t stride) {
+  if (H <= 0 || W <= 0 || stride <= 0) return 0;
+  return 4 * ingest_scratch_words(H, W, stride);
+}
+
+int vtgs_ingest_count(const float *depth_img, const uint8_t *mask, int32_t H, int32_t W,
+                      int32_t stride, void *scratch, int64_t scratch_bytes, int32_t *count,
+                      void *stream) {
+  try {
+    if (!depth_img || !scratch || !count) return fail(VTGS_E_ARG, "ingest_count: NULL pointer");
+    if (H <= 0 || W <= 0 || stride <= 0 || (int64_t)H * W > (1ll << 31) - 1)
+      return fail(VTGS_E_ARG, "ingest_count: need H, W, stride > 0 and H*W < 2^31");
+    if (scratch_bytes < vtgs_ingest_scratch_bytes(H, W, stride))
+      return fail(VTGS_E_WORKSPACE, "ingest_count: scratch too small");
+    HIP_OK(launch_ingest_count(depth_img, mask, H, W, stride, (uint32_t *)scratch, count,
+                               (hipStream_t)stream));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "ingest_count: unexpected exception");
+  }
+}
+
+int vtgs_ingest_fill(const float *depth_img, const float *rgb_img, const uint8_t *mask,
+                     int32_t H, int32_t W, int32_t stride, float fx, float o_init,
+                     const void *scratch, int64_t scratch_bytes, int32_t n, uint32_t *pix,
+                     float *depth, float *color, float *opacity, float *radius, void *stream) {
+  try {
+    if (!depth_img || !scratch) return fail(VTGS_E_ARG, "ingest_fill: NULL pointer");
+    if (n > 0 && (!pix || !depth || !opacity || !radius || (rgb_img && !color)))
+      return fail(VTGS_E_ARG, "ingest_fill: NULL output pointer");
+    if (H <= 0 || W <= 0 || stride <= 0 || n < 0 || (int64_t)H * W > (1ll << 31) - 1)
+      return fail(VTGS_E_ARG, "ingest_fill: need H, W, stride > 0, n >= 0");
+    if (!finite_pos(fx)) return fail(VTGS_E_ARG, "ingest_fill: fx must be finite and > 0");
+    if (scratch_bytes < vtgs_ingest_scratch_bytes(H, W, stride))
+      return fail(VTGS_E_WORKSPACE, "ingest_fill: scratch too small");
+    HIP_OK(launch_ingest_fill(depth_img, rgb_img, mask, H, W, stride, fx, o_init,
+                              (const uint32_t *)scratch, n, pix, depth, color, opacity, radius,
+                              (hipStream_t)stream));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "ingest_fill: unexpected exception");
+  }
+}
+
+int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *views,
+                     int32_t n_views, const vtgs_params *prm, int64_t pair_capacity,
+                     vtgs_plan **out) {
+  try {
+    if (!out) return fail(VTGS_E_ARG, "plan_create: out is NULL");
+    *out = nullptr;
+    if (n_kf < 0 || n_views < 1 || (n_kf > 0 && !kfs) || !views)
+      return fail(VTGS_E_ARG, "plan_create: need n_kf >= 0, n_views >= 1 and their arrays");
+    vtgs_params P;
+    if (prm) P = *prm; else vtgs_default_params(&P);
+    if (P.tile != 8 && P.tile != 16 && P.tile != 32)
+      return fail(VTGS_E_ARG, "plan_create: tile must be 8, 16 or 32");
+    if (P.batch != 128 && P.batch != 256 && P.batch != 512)
+      return fail(VTGS_E_ARG, "plan_create: batch must be 128, 256 or 512");
+    if (!(P.alpha_min >= 0.f && P.alpha_max >= P.alpha_min && P.alpha_max < 1.f && P.t_min >= 0.f &&
+          P.t_min < 1.f && P.q_cut > 0.f && std::isfinite(P.q_cut) && P.lowpass >= 0.f &&
+          std::isfinite(P.lowpass) && std::isfinite(P.z_near)))
+      return fail(VTGS_E_ARG, "plan_create: need 0 <= alpha_min <= alpha_max < 1, 0 <= t_min < 1, "
+                              "finite q_cut > 0, lowpass >= 0, finite z_near");
+    auto *p = new vtgs_plan();
+    p->prm = P;
+    int64_t n_rec = 0, n_tiles = 0, Ptot = 0;
+    int32_t loss_blocks = 0, maxw = 0, maxh = 0;
+    for (int k = 0; k < n_kf; k++) {
+      const vtgs_keyframe &K = kfs[k];
+      if (K.n < 0) { delete p; return fail(VTGS_E_ARG, "plan_create: keyframe " + std::to_string(k) + " has n < 0"); }
+      if (int rc = validate_cam(K.cam, "keyframe", k)) { delete p; return rc; }
+      if (K.n > 0 && (!K.pix || !K.depth || !K.color || !K.opacity || !K.radius || !K.pose)) {
+        delete p;
+        return fail(VTGS_E_ARG, "plan_create: keyframe " + std::to_string(k) + " has a NULL array");
+      }
+      if (K.n > 0 && !K.pose) { delete p; return fail(VTGS_E_ARG, "plan_create: keyframe pose NULL"); }
+      DevKF d{};
+      d.pix = K.pix; d.depth = K.depth; d.color = K.color; d.opacity = K.opacity;
+      d.radius = K.radius; d.pose = K.pose;
+      d.fx = K.cam.fx; d.fy = K.cam.fy; d.cx = K.cam.cx; d.cy = K.cam.cy;
+      d.width = K.cam.width; d.height = K.cam.height; d.n = K.n; d.learnable = K.learnable ? 1 : 0;
+      d.g_color = K.g_color; d.g_opacity = K.g_opacity; d.g_radius = K.g_radius; d.adam = K.adam;
+      p->kfs.push_back(d);
+      if (d.learnable && d.n > 0) {
+        p->any_learnable = true;
+        p->max_learn_n = std::max(p->max_learn_n, d.n);
+      }
+    }
+    for (int v = 0; v < n_views; v++) {
+      const vtgs_view &V = views[v];
+      if (int rc = validate_cam(V.cam, "view", v)) { delete p; return rc; }
+      if (!V.pose) { delete p; return fail(VTGS_E_ARG, "plan_create: view " + std::to_string(v) + " pose is NULL"); }
+      if (V.kf_first < 0 || V.kf_count < 0 || (int64_t)V.kf_first + V.kf_count > n_kf) {
+        delete p;
+        return fail(VTGS_E_ARG, "plan_create: view " + std::to_string(v) + " keyframe slice out of range");
+      }
+      DevView d{};
+      d.fx = V.cam.fx; d.fy = V.cam.fy; d.cx = V.cam.cx; d.cy = V.cam.cy;
+      d.width = V.cam.width; d.height = V.cam.height;
+      d.tiles_x = (V.cam.width + P.tile - 1) / P.tile;
+      d.tiles_y = (V.cam.height + P.tile - 1) / P.tile;
+      d.pose = V.pose; d.kf_first = V.kf_first; d.kf_count = V.kf_count;
+      d.rec_base = (int32_t)n_rec;
+      d.tile_base = (int32_t)n_tiles;
+      d.n_tiles = d.tiles_x * d.tiles_y;
+      d.pix_off = Ptot;
+      d.obs_rgb = V.obs_rgb; d.obs_depth = V.obs_depth; d.vis = V.vis; d.pose_adam = V.pose_adam;
+      d.seg_first = (int32_t)p->segs.size();
+      d.seg_count = V.kf_count;
+      int64_t local = 0;
+      for (int s = 0; s < V.kf_count; s++) {
+        const int k = V.kf_first + s;
+        DevSeg sg{};
+        sg.view = v; sg.kf = k; sg.rec_start = (int32_t)(n_rec + local); sg.n = kfs[k].n;
+        p->segs.push_back(sg);
+        local += kfs[k].n;
+      }
+      d.n_rec = (int32_t)local;
+      n_rec += local;
+      n_tiles += d.n_tiles;
+      const int64_t Pv = (int64_t)V.cam.width * V.cam.height;
+      Ptot += Pv;
+      loss_blocks = std::max<int32_t>(loss_blocks, (int32_t)((Pv + 255) / 256));
+      maxw = std::max(maxw, V.cam.width);
+      maxh = std::max(maxh, V.cam.height);
+      if (n_rec > (1ll << 31) - 1 || n_tiles > (1ll << 31) - 1 || Ptot > (1ll << 31) - 1) {
+        delete p;
+        return fail(VTGS_E_ARG, "plan_create: more than 2^31 records, tiles or pixels");
+      }
+      p->views.push_back(d);
+    }
+    // per keyframe, the (view, record start) pairs that render it
+    p->kf_use_off.assign(n_kf + 1, 0);
+    for (const DevSeg &s : p->segs) p->kf_use_off[s.kf + 1]++;
+    for (int k = 0; k < n_kf; k++) p->kf_use_off[k + 1] += p->kf_use_off[k];
+    p->kf_use.resize(p->segs.size());
+    {
+      std::vector<int32_t> fill(p->kf_use_off.begin(), p->kf_use_off.end() - 1);
+      for (const DevSeg &s : p->segs) p->kf_use[fill[s.kf]++] = DevKFUse{s.rec_start, s.view};
+    }
+    p->n_rec = (int32_t)n_rec;
+    p->n_tiles = (int32_t)n_tiles;
+    p->P = Ptot;
+    p->loss_blocks = std::max(loss_blocks, 1);
+    p->ssim_gx = (maxw + 15) / 16;
+    p->ssim_gy = (maxh + 15) / 16;
+    // default room: a Gaussian of extent R ~ 4-5 px covers about (1 + 10/B)^2
+    // tiles of side B; keep 50% headroom
+    const double per = 1.5 * (1.0 + 10.0 / P.tile) * (1.0 + 10.0 / P.tile);
+    int64_t cap = pair_capacity > 0 ? pair_capacity : (int64_t)std::ceil(per * (double)n_rec) + 65536;
+    cap = std::max<int64_t>(cap, 1);
+    if (cap > 0xFFFFFFFFll) cap = 0xFFFFFFFFll;
+    p->cap = cap;
+    layout(p);
+    *out = p;
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "plan_create: unexpected exception (out of host memory?)");
+  }
+}
+
+void vtgs_plan_destroy(vtgs_plan *p) {
+  if (!p) return;
+  if (p->upload_done) {
+    (void)hipEventSynchronize(p->upload_done);
+    (void)hipEventDestroy(p->upload_done);
+  }
+  if (p->pinned) (void)hipHostFree(p->pinned);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  delete p;
+}
+
+int64_t vtgs_plan_workspace_bytes(const vtgs_plan *p) { return p ? p->ws_bytes : -1; }
+int64_t vtgs_plan_pixels(const vtgs_plan *p) { return p ? p->P : -1; }
+int64_t vtgs_plan_records(const vtgs_plan *p) { return p ? p->n_rec : -1; }
+int64_t vtgs_plan_tiles(const vtgs_plan *p) { return p ? p->n_tiles : -1; }
+int64_t vtgs_plan_pair_capacity(const vtgs_plan *p) { return p ? p->cap : -1; }
+int64_t vtgs_plan_view_offset(const vtgs_plan *p, int32_t v) {
+  if (!p || v < 0 || v >= (int32_t)p->views.size()) return -1;
+  return p->views[v].pix_off;
+}
+
+int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
+  try {
+    if (!p) return fail(VTGS_E_ARG, "plan_bind: plan is NULL");
+    if (!ws) return fail(VTGS_E_WORKSPACE, "plan_bind: workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+      return fail(VTGS_E_WORKSPACE, "plan_bind: workspace must be 256-byte aligned");
+    if (ws_bytes < p->ws_bytes)
+      return fail(VTGS_E_WORKSPACE, "plan_bind: workspace has " + std::to_string(ws_bytes) +
+                                        " bytes, needs " + std::to_string(p->ws_bytes));
+    hipStream_t st = (hipStream_t)stream;
+    if (p->upload_done) HIP_OK(hipEventSynchronize(p->upload_done));
+    if (!p->pinned) HIP_OK(hipHostMalloc(&p->pinned, std::max<int64_t>(p->desc_bytes, 256)));
+    if (!p->upload_done) HIP_OK(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming));
+    char *h = (char *)p->pinned;
+    std::memset(h, 0, p->desc_bytes);
+    if (!p->kfs.empty()) std::memcpy(h + p->desc_kf, p->kfs.data(), p->kfs.size() * sizeof(DevKF));
+    std::memcpy(h + p->desc_view, p->views.data(), p->views.size() * sizeof(DevView));
+    if (!p->segs.empty()) std::memcpy(h + p->desc_seg, p->segs.data(), p->segs.size() * sizeof(DevSeg));
+    std::memcpy(h + p->desc_use_off, p->kf_use_off.data(), p->kf_use_off.size() * 4);
+    if (!p->kf_use.empty()) std::memcpy(h + p->desc_use, p->kf_use.data(), p->kf_use.size() * sizeof(DevKFUse));
+    p->ws = (char *)ws;
+    make_ws(p);
+    HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
+    HIP_OK(hipEventRecord(p->upload_done, st));
+    HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
+    HIP_OK(launch_fill_u32(p->w.tile_count, 0u, p->n_tiles, st));
+    HIP_OK(launch_fill_u32(p->w.tile_fill, 0u, p->n_tiles, st));
+    p->bound = true;
+    p->fwd_done = false;
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "plan_bind: unexpected exception");
+  }
+}
+
+int vtgs_plan_status(vtgs_plan *p, int64_t *pairs_needed, int32_t clear, void *stream) {
+  if (int rc = check_bound(p)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_OK(hipStreamSynchronize(st));
+  uint32_t flags = 0;
+  unsigned long long np = 0;
+  HIP_OK(hipMemcpy(&flags, p->w.flags, 4, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(&np, p->w.n_pairs, 8, hipMemcpyDeviceToHost));
+  if (pairs_needed) *pairs_needed = (int64_t)np;
+  if (clear && flags) {
+    HIP_OK(launch_fill_u32(p->w.flags, 0u, 1, st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  if (flags & kFlagCapacity)
+    return fail(VTGS_E_CAPACITY, "pair capacity " + std::to_string(p->cap) + " exceeded: " +
+                                     std::to_string(np) + " (Gaussian, tile) pairs needed");
+  if (flags & kFlagNonfinite) return fail(VTGS_E_NONFINITE, "a loss was not finite");
+  return VTGS_OK;
+}
+
+int vtgs_render_fwd(vtgs_plan *p, float *rgb, float *depth, float *sil, void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    return run_forward(p, rgb, depth, sil, (hipStream_t)stream);
+  } catch (...) {
+    return fail(VTGS_E_HIP, "render_fwd: unexpected exception");
+  }
+}
+
+int vtgs_render_bwd(vtgs_plan *p, const float *g_rgb, const float *g_depth, const float *g_sil,
+                    float *g_twist, void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    if (!p->fwd_done) return fail(VTGS_E_ARG, "render_bwd: no render_fwd on this plan yet");
+    hipStream_t st = (hipStream_t)stream;
+    bool want_kf = false;
+    for (const DevKF &k : p->kfs)
+      if (k.learnable && k.n > 0 && (k.g_color || k.g_opacity || k.g_radius)) want_kf = true;
+    const int mode = (g_twist ? 1 : 0) | (want_kf ? 2 : 0);
+    if (mode == 0) return VTGS_OK;
+    const Ws &w = p->w;
+    if (mode & 2) STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
+    STAGE(p, ST_BWD, st, launch_composite_bwd(w, g_rgb, g_depth, g_sil, mode, st));
+    if (mode & 2) STAGE(p, ST_REDUCE, st, launch_gather(w, p->max_learn_n, st));
+    if (mode & 1) STAGE(p, ST_REDUCE, st, launch_twist_reduce(w, g_twist, st));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "render_bwd: unexpected exception");
+  }
+}
+
+int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, float *loss,
+                    void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    if (!cfg) return fail(VTGS_E_ARG, "track_step: cfg is NULL");
+    if (iters < 0) return fail(VTGS_E_ARG, "track_step: iters < 0");
+    for (size_t v = 0; v < p->views.size(); v++) {
+      const DevView &d = p->views[v];
+      if (!d.obs_rgb || !d.obs_depth || !d.pose_adam)
+        return fail(VTGS_E_ARG, "track_step: view " + std::to_string(v) +
+                                    " needs obs_rgb, obs_depth and pose_adam");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const Ws &w = p->w;
+    const int64_t P = p->P;
+    for (int it = 0; it < iters; it++) {
+      if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
+      STAGE(p, ST_LOSS, st, launch_track_loss(w, *cfg, st));
+      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 1, st));
+      STAGE(p, ST_UPDATE, st,
+            launch_track_update(w, *cfg, loss ? loss + (int64_t)it * p->views.size() : nullptr, st));
+    }
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "track_step: unexpected exception");
+  }
+}
+
+int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *loss,
+                  void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    if (!cfg || !step) return fail(VTGS_E_ARG, "map_step: cfg and step are required");
+    for (size_t v = 0; v < p->views.size(); v++) {
+      const DevView &d = p->views[v];
+      if (!d.obs_rgb || !d.obs_depth)
+        return fail(VTGS_E_ARG, "map_step: view " + std::to_string(v) + " needs obs_rgb and obs_depth");
+    }
+    for (size_t k = 0; k < p->kfs.size(); k++)
+      if (p->kfs[k].learnable && p->kfs[k].n > 0 && !p->kfs[k].adam)
+        return fail(VTGS_E_ARG, "map_step: learnable keyframe " + std::to_string(k) + " has no adam state");
+    hipStream_t st = (hipStream_t)stream;
+    const Ws &w = p->w;
+    const int64_t P = p->P;
+    if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
+    STAGE(p, ST_LOSS, st, launch_map_loss(w, *cfg, st));
+    if (p->any_learnable) {
+      STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
+      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 2, st));
+    }
+    STAGE(p, ST_UPDATE, st,
+          launch_map_update(w, *cfg, step, loss, p->any_learnable ? p->max_learn_n : 0, st));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "map_step: unexpected exception");
+  }
+}
+
+const char *vtgs_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < ST_N) ? kStageNames[stage] : "";
+}
+
+int vtgs_plan_timing(vtgs_plan *p, int32_t enable, double *ms, int64_t *count) {
+  try {
+    if (!p) return fail(VTGS_E_ARG, "plan_timing: plan is NULL");
+    if (enable) {
+      p->timing = true;
+      p->ev_used.clear();
+      return VTGS_OK;
+    }
+    p->timing = false;
+    double acc[ST_N] = {0};
+    int64_t cnt[ST_N] = {0};
+    for (auto &u : p->ev_used) {
+      HIP_OK(hipEventSynchronize(p->ev_pool[u.second.second]));
+      float t = 0.f;
+      HIP_OK(hipEventElapsedTime(&t, p->ev_pool[u.second.first], p->ev_pool[u.second.second]));
+      acc[u.first] += t;
+      cnt[u.first] += 1;
+    }
+    p->ev_used.clear();
+    for (int i = 0; i < ST_N; i++) {
+      if (ms) ms[i] = acc[i];
+      if (count) count[i] = cnt[i];
+    }
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "plan_timing: unexpected exception");
+  }
+}
+
+int vtgs_debug_state(vtgs_plan *p, float *records, int32_t *rect, uint32_t *ranges, uint32_t *ids,
+                     int64_t *n_pairs, void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (records || rect) HIP_OK(launch_debug_copy(p->w, records, rect, st));
+    if (ranges) HIP_OK(hipMemcpyAsync(ranges, p->w.ranges, (size_t)p->n_tiles * 8, hipMemcpyDeviceToDevice, st));
+    if (ids) HIP_OK(hipMemcpyAsync(ids, p->w.ids, (size_t)p->cap * 4, hipMemcpyDeviceToDevice, st));
+    if (n_pairs) HIP_OK(hipMemcpyAsync(n_pairs, p->w.n_pairs, 8, hipMemcpyDeviceToDevice, st));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "debug_state: unexpected exception");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,419 @@
+// Preprocessing and tile binning of view-tied Gaussians.
+//
+//  setup      M_vk = T_v T_k^-1 for every (view, keyframe) pair
+//  preprocess per (view, Gaussian): back-project the tied depth pixel with
+//             the keyframe pose (Sec. 3.2), move it to the view camera,
+//             project, Sigma_2D = r^2 J J^T + lowpass*I, conic, extent
+//             R = ceil(sqrt(q_cut * lambda_max)), tile rectangle; then count
+//             the Gaussian in each tile it covers (wave-aggregated atomics)
+//  scan_tiles exclusive scan of the tile counts -> per-tile [start, end)
+//  fill_keys  write (depth bits << 32 | view-local id) into the tile slots
+//  sort_tiles sort each tile's keys (ascending depth, ties by id) in LDS and
+//             emit the id list the compositing kernels walk
+//  scan_recs  exclusive scan of tiles per record (gradient slot offsets)
+//
+// Every floating-point operation that decides a tile or a record is
+// written in a fixed order and compiled without contraction, so the tile
+// lists are bit-identical to an IEEE single-precision evaluation of the same
+// expressions.
+#include "vtgs_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace vtgs {
+
+namespace {
+
+constexpr int kNT = 256;
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// M = Tv * Tk^-1 = [Rv Rk^T | tv - (Rv Rk^T) tk], fixed summation order.
+__global__ void k_setup(Ws ws) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ws.n_segs) return;
+  DevSeg &sg = ws.segs[s];
+  const float *Tv = ws.views[sg.view].pose;
+  const float *Tk = ws.kfs[sg.kf].pose;
+  float tv[12], tk[12], M[12];
+  for (int i = 0; i < 12; i++) { tv[i] = Tv[i]; tk[i] = Tk[i]; }
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++)
+      M[4 * i + j] = (tv[4 * i + 0] * tk[4 * j + 0] + tv[4 * i + 1] * tk[4 * j + 1]) +
+                     tv[4 * i + 2] * tk[4 * j + 2];
+  for (int i = 0; i < 3; i++)
+    M[4 * i + 3] = tv[4 * i + 3] -
+                   ((M[4 * i + 0] * tk[3] + M[4 * i + 1] * tk[7]) + M[4 * i + 2] * tk[11]);
+  for (int i = 0; i < 12; i++) sg.M[i] = M[i];
+}
+
+__device__ __forceinline__ int find_seg(const Ws &ws, int r) {
+  int lo = 0, hi = ws.n_segs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ws.segs[mid].rec_start <= r) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1, int &y1) {
+  x0 = rc.x & 0xffff; y0 = rc.x >> 16; x1 = rc.y & 0xffff; y1 = rc.y >> 16;
+}
+
+// Visit every tile covered by the active lanes' rectangles.  When the whole
+// wave belongs to one view and its rectangles fit in a small bounding box,
+// each tile is handled once per wave: `f(tile, mask)` runs on every lane
+// with the ballot of lanes covering that tile (same value in all lanes).
+// Otherwise each lane visits its own tiles with mask = its own bit.
+template <typename F>
+__device__ __forceinline__ void for_tiles(bool has, int view, int x0, int y0, int x1, int y1,
+                                          int tiles_x, F &&f) {
+  const int vmin = wave_min_i(has ? view : 0x7fffffff);
+  const int vmax = wave_max_i(has ? view : -1);
+  if (vmax < 0) return;
+  const int bx0 = wave_min_i(has ? x0 : 0x7fffffff), by0 = wave_min_i(has ? y0 : 0x7fffffff);
+  const int bx1 = wave_max_i(has ? x1 : -1), by1 = wave_max_i(has ? y1 : -1);
+  const long area = (long)(bx1 - bx0 + 1) * (long)(by1 - by0 + 1);
+  if (vmin == vmax && area <= 24) {
+    for (int ty = by0; ty <= by1; ty++)
+      for (int tx = bx0; tx <= bx1; tx++) {
+        const bool in = has && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
+        const unsigned long long m = ballot64(in);
+        if (m) f(ty * tiles_x + tx, m, in);
+      }
+  } else if (has) {
+    const unsigned long long me = 1ull << lane_id();
+    for (int ty = y0; ty <= y1; ty++)
+      for (int tx = x0; tx <= x1; tx++) f(ty * tiles_x + tx, me, true);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
+  const int r = blockIdx.x * kNT + threadIdx.x;
+  const bool active = r < ws.n_rec;
+  bool has = false;
+  int view = 0, x0 = 1, y0 = 0, x1 = 0, y1 = 0, tiles_x = 1, tile_base = 0;
+  if (active) {
+    const DevSeg &sg = ws.segs[find_seg(ws, r)];
+    const DevKF &kf = ws.kfs[sg.kf];
+    const DevView &vw = ws.views[sg.view];
+    view = sg.view;
+    tiles_x = vw.tiles_x;
+    tile_base = vw.tile_base;
+    const int i = r - sg.rec_start;
+    const uint32_t pix = kf.pix[i];
+    const float d = kf.depth[i];
+    const float rad = kf.radius[i];
+    const int u = (int)(pix % (uint32_t)kf.width), v = (int)(pix / (uint32_t)kf.width);
+    // back-projection of the tied depth pixel (keyframe camera)
+    const float xk = (((float)u - kf.cx) / kf.fx) * d;
+    const float yk = (((float)v - kf.cy) / kf.fy) * d;
+    const float zk = d;
+    const float *M = sg.M;
+    const float px = ((M[0] * xk + M[1] * yk) + M[2] * zk) + M[3];
+    const float py = ((M[4] * xk + M[5] * yk) + M[6] * zk) + M[7];
+    const float pz = ((M[8] * xk + M[9] * yk) + M[10] * zk) + M[11];
+    float mx = 0.f, my = 0.f, qa = 0.f, qb = 0.f, qc = 0.f, R = 0.f;
+    if (pz > ws.znear) {
+      mx = vw.fx * (px / pz) + vw.cx;
+      my = vw.fy * (py / pz) + vw.cy;
+      const float a = vw.fx / pz, b = vw.fy / pz;
+      const float zz = pz * pz;
+      const float jx = -(vw.fx * px) / zz, jy = -(vw.fy * py) / zz;
+      const float r2 = rad * rad;
+      const float s11 = r2 * (a * a + jx * jx) + ws.lowpass;
+      const float s12 = r2 * (jx * jy);
+      const float s22 = r2 * (b * b + jy * jy) + ws.lowpass;
+      const float det = s11 * s22 - s12 * s12;
+      if (det > 0.f) {
+        const float mid = 0.5f * (s11 + s22);
+        const float lmax = mid + sqrtf(fmaxf(0.f, mid * mid - det));
+        R = ceilf(sqrtf(ws.qcut * lmax));
+        if (__builtin_isfinite(mx) && __builtin_isfinite(my) && __builtin_isfinite(R)) {
+          qa = s22 / det; qb = -s12 / det; qc = s11 / det;
+          const float invB = 1.0f / (float)ws.tile;
+          const float fx0 = fmaxf(floorf((mx - R) * invB), 0.f);
+          const float fy0 = fmaxf(floorf((my - R) * invB), 0.f);
+          const float fx1 = fminf(floorf((mx + R) * invB), (float)(vw.tiles_x - 1));
+          const float fy1 = fminf(floorf((my + R) * invB), (float)(vw.tiles_y - 1));
+          if (!(fx0 > fx1 || fy0 > fy1)) {
+            x0 = (int)fx0; y0 = (int)fy0; x1 = (int)fx1; y1 = (int)fy1;
+            has = true;
+          }
+        }
+      }
+    }
+    const float o = kf.opacity[i];
+    float4 *A = ws.recA + 3 * (int64_t)r;
+    A[0] = make_float4(mx, my, qa, qb);
+    A[1] = make_float4(qc, o, pz, R);
+    A[2] = make_float4(kf.color[i], kf.color[(int64_t)kf.n + i], kf.color[2 * (int64_t)kf.n + i],
+                       rad);
+    ws.recB[r] = make_float4(px, py, kf.learnable ? 1.f : 0.f, 0.f);
+    if (!has) { x0 = 1; y0 = 0; x1 = 0; y1 = 0; }
+    ws.rect[r] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
+    ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+  }
+  uint32_t *cnt = ws.tile_count + tile_base;
+  for_tiles(has, view, x0, y0, x1, y1, tiles_x,
+            [&](int t, unsigned long long m, bool in) {
+              if (lane_id() == __ffsll((long long)m) - 1) atomicAdd(cnt + t, (uint32_t)__popcll(m));
+            });
+}
+
+// One block: tile counts -> ranges (clamped to the pair capacity), total
+// pairs, capacity flag; clears the counters for the next pass.
+constexpr int kScanNT = 1024, kScanPer = 8;
+__global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
+  __shared__ uint32_t lw[kScanNT / kWave];
+  __shared__ unsigned long long carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int base = 0; base < ws.n_tiles; base += kScanNT * kScanPer) {
+    const int i0 = base + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer], sum = 0;
+    for (int k = 0; k < kScanPer; k++) {
+      v[k] = (i0 + k < ws.n_tiles) ? ws.tile_count[i0 + k] : 0u;
+      sum += v[k];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kScanNT>(sum, lw, &tot);
+    const unsigned long long c = carry_s;
+    unsigned long long pos = c + ex;
+    for (int k = 0; k < kScanPer; k++) {
+      const int i = i0 + k;
+      if (i < ws.n_tiles) {
+        const unsigned long long s = pos < (unsigned long long)ws.cap ? pos : ws.cap;
+        const unsigned long long e = pos + v[k] < (unsigned long long)ws.cap ? pos + v[k] : ws.cap;
+        ws.ranges[i] = make_uint2((uint32_t)s, (uint32_t)e);
+        ws.tile_count[i] = 0;
+        ws.tile_fill[i] = 0;
+      }
+      pos += v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = c + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *ws.n_pairs = carry_s;
+    if (carry_s > (unsigned long long)ws.cap) atomicOr(ws.flags, kFlagCapacity);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
+  const int r = blockIdx.x * kNT + threadIdx.x;
+  const bool active = r < ws.n_rec;
+  bool has = false;
+  int view = 0, x0 = 1, y0 = 0, x1 = 0, y1 = 0, tiles_x = 1, tile_base = 0;
+  unsigned long long key = 0;
+  if (active) {
+    unpack_rect(ws.rect[r], x0, y0, x1, y1);
+    has = x0 <= x1;
+    view = find_view_by_record(ws, r);
+    const DevView &vw = ws.views[view];
+    tiles_x = vw.tiles_x;
+    tile_base = vw.tile_base;
+    const float z = ws.recA[3 * (int64_t)r + 1].z;
+    key = ((unsigned long long)__float_as_uint(z) << 32) | (uint32_t)(r - vw.rec_base);
+  }
+  for_tiles(has, view, x0, y0, x1, y1, tiles_x,
+            [&](int t, unsigned long long m, bool in) {
+              const int leader = __ffsll((long long)m) - 1;
+              uint32_t base = 0;
+              if (lane_id() == leader) {
+                const uint32_t slot = atomicAdd(ws.tile_fill + tile_base + t, (uint32_t)__popcll(m));
+                base = ws.ranges[tile_base + t].x + slot;
+              }
+              base = (uint32_t)__shfl((int)base, leader);
+              if (in) {
+                const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
+                if (pos < ws.ranges[tile_base + t].y) ws.keys[pos] = key;
+              }
+            });
+}
+
+// Bitonic sort with ascending comparators only (a flip stage then
+// half-cleaners), so indices >= n behave as +infinity and need no padding.
+template <typename T>
+__device__ __forceinline__ void bitonic_sort(T *s, int n) {
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int k = 2; k <= np; k <<= 1) {
+    const int half = k >> 1;
+    for (int c = threadIdx.x; c < np / 2; c += blockDim.x) {
+      const int i = (c / half) * k + (c % half);
+      const int p = i + (k - 1 - 2 * (c % half));
+      if (p < n) {
+        const auto a = s[i], b = s[p];
+        if (b < a) { s[i] = b; s[p] = a; }
+      }
+    }
+    __syncthreads();
+    for (int j = half >> 1; j > 0; j >>= 1) {
+      for (int c = threadIdx.x; c < np / 2; c += blockDim.x) {
+        const int i = (c / j) * 2 * j + (c % j);
+        const int p = i + j;
+        if (p < n) {
+          const auto a = s[i], b = s[p];
+          if (b < a) { s[i] = b; s[p] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+constexpr int kSortCap = 8192;
+__global__ __launch_bounds__(kNT) void k_sort_tiles(Ws ws) {
+  __shared__ unsigned long long s[kSortCap];
+  // ranges are clamped to the capacity, and every position of a clamped
+  // range was written by the fill, so sorting stays in bounds on overflow
+  const uint2 rg = ws.ranges[blockIdx.x];
+  const int n = (int)(rg.y - rg.x);
+  if (n <= 0) return;
+  const unsigned long long *src = ws.keys + rg.x;
+  uint32_t *dst = ws.ids + rg.x;
+  if (n <= kSortCap) {
+    for (int i = threadIdx.x; i < n; i += kNT) s[i] = src[i];
+    __syncthreads();
+    bitonic_sort(s, n);
+    for (int i = threadIdx.x; i < n; i += kNT) dst[i] = (uint32_t)s[i];
+  } else {
+    unsigned long long *g = ws.keys_tmp + rg.x;
+    for (int i = threadIdx.x; i < n; i += kNT) g[i] = src[i];
+    __syncthreads();
+    bitonic_sort(g, n);
+    for (int i = threadIdx.x; i < n; i += kNT) dst[i] = (uint32_t)g[i];
+  }
+}
+
+// Device-wide exclusive scan of rec_cnt -> rec_off (3 phases).
+constexpr int kRecPer = 8, kRecBlock = kNT * kRecPer;
+__global__ __launch_bounds__(kNT) void k_rec_scan_a(Ws ws) {
+  __shared__ uint32_t lw[kNT / kWave];
+  const int64_t i0 = (int64_t)blockIdx.x * kRecBlock + threadIdx.x * kRecPer;
+  uint32_t s = 0;
+  for (int k = 0; k < kRecPer; k++)
+    if (i0 + k < ws.n_rec) s += ws.rec_cnt[i0 + k];
+  uint32_t tot;
+  block_exclusive_scan<kNT>(s, lw, &tot);
+  if (threadIdx.x == 0) ws.scan_part[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(1024) void k_rec_scan_b(Ws ws, int nb) {
+  __shared__ uint32_t lw[1024 / kWave];
+  uint32_t carry = 0;
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nb ? ws.scan_part[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(v, lw, &tot);
+    if (i < nb) ws.scan_part[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ws.rec_off[ws.n_rec] = carry;
+}
+__global__ __launch_bounds__(kNT) void k_rec_scan_c(Ws ws) {
+  __shared__ uint32_t lw[kNT / kWave];
+  const int64_t i0 = (int64_t)blockIdx.x * kRecBlock + threadIdx.x * kRecPer;
+  uint32_t v[kRecPer], s = 0;
+  for (int k = 0; k < kRecPer; k++) {
+    v[k] = (i0 + k < ws.n_rec) ? ws.rec_cnt[i0 + k] : 0u;
+    s += v[k];
+  }
+  uint32_t pos = ws.scan_part[blockIdx.x] + block_exclusive_scan<kNT>(s, lw, nullptr);
+  for (int k = 0; k < kRecPer; k++) {
+    if (i0 + k < ws.n_rec) ws.rec_off[i0 + k] = pos;
+    pos += v[k];
+  }
+}
+
+__global__ void k_debug_copy(Ws ws, float *records, int32_t *rect) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= ws.n_rec) return;
+  if (records) {
+    const float4 a = ws.recA[3 * (int64_t)r], b = ws.recA[3 * (int64_t)r + 1],
+                 c = ws.recA[3 * (int64_t)r + 2];
+    float *o = records + 12 * (int64_t)r;
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+    o[8] = c.x; o[9] = c.y; o[10] = c.z; o[11] = c.w;
+  }
+  if (rect) {
+    int x0, y0, x1, y1;
+    unpack_rect(ws.rect[r], x0, y0, x1, y1);
+    int32_t *o = rect + 4 * (int64_t)r;
+    o[0] = x0; o[1] = y0; o[2] = x1; o[3] = y1;
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, kNT)), dim3(kNT), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, kNT)), dim3(kNT), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(const Ws &ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(blocks_for(ws.n_segs, 64)), dim3(64), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const Ws &ws, hipStream_t st) {
+  if (ws.n_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_tiles(const Ws &ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanNT), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
+  if (ws.n_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_keys, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_sort_tiles, dim3(ws.n_tiles), dim3(kNT), 0, st, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_records(const Ws &ws, hipStream_t st) {
+  const int nb = (int)blocks_for(ws.n_rec, kRecBlock);
+  if (nb == 0) return launch_fill_u32(ws.rec_off, 0u, 1, st);
+  hipLaunchKernelGGL(k_rec_scan_a, dim3(nb), dim3(kNT), 0, st, ws);
+  hipLaunchKernelGGL(k_rec_scan_b, dim3(1), dim3(1024), 0, st, ws, nb);
+  hipLaunchKernelGGL(k_rec_scan_c, dim3(nb), dim3(kNT), 0, st, ws);
+  return hipGetLastError();
+}
+
+int64_t rec_scan_blocks(int64_t n_rec) { return (n_rec + kRecBlock - 1) / kRecBlock; }
+
+hipError_t launch_debug_copy(const Ws &ws, float *records, int32_t *rect, hipStream_t st) {
+  if (ws.n_rec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_debug_copy, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws,
+                     records, rect);
+  return hipGetLastError();
+}
+
+}  // namespace vtgs

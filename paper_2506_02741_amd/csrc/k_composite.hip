@@ -1,0 +1,458 @@
+// Tile compositing of view-tied Gaussians: forward (RGB, depth, silhouette)
+// and its reverse-mode replay.
+//
+// One workgroup per (view, tile).  Each wave owns a square block of the
+// tile (8x8 pixels, or 16x16 for 32-pixel tiles with four pixels per lane);
+// a Gaussian whose extent box misses that block is skipped by the whole
+// wave with a scalar branch.  The tile's depth-sorted list is walked in
+// batches staged through LDS.
+//
+// Forward, per pixel, front to back [splat of Sec. 3.3]:
+//   q = d^T Q d with d = pixel - mu; skip q > q_cut
+//   alpha = min(alpha_max, o exp(-q/2)); skip alpha < alpha_min
+//   stop before T (1 - alpha) < t_min
+//   C += c alpha T, D += z alpha T, T *= (1 - alpha)
+//   out: C + T bg, D, 1 - T; keep T_final and the list position past the
+//   last contributor for the backward.
+//
+// Backward replays the same list from the last contributor towards the
+// front, recovering T_i = T_{i+1} / (1 - alpha_i) and keeping the colour,
+// depth and coverage of everything behind i, B <- alpha x + (1 - alpha) B.
+// Per contributing pair:
+//   dL/dalpha = T [g_C.(c - B_C) + g_D (z - B_D) + g_S (1 - B_S)]
+//   dL/dc = alpha T g_C, dL/dz = alpha T g_D,
+//   if o G <= alpha_max: dL/do = G dL/dalpha, dL/dq = -o G dL/dalpha / 2
+// and q's dependence on the camera-frame centre p and the radius r
+// (mu = proj(p), Sigma = r^2 J J^T + s I, w = Sigma^-1 d, t = J^T w):
+//   dq/dr = -2 r |t|^2
+//   dq/dp = (-2 t0 + k t0 t2, -2 t1 + k t1 t2, -2 t2 + k (t0^2 + t1^2 + 2 t2^2)),
+//   k = 2 r^2 / p_z.
+// Mode "twist": dL/dp is chained straight to the view's left twist
+// (rho += dL/dp, phi += p x dL/dp) in registers, summed per tile.
+// Mode "slots": (dL/dc, dL/do, dL/dr) are summed over the wave, then over
+// the four waves, and written to the pair's (record, tile) slot; a gather
+// pass sums a record's slots.  Neither mode uses global atomics, so both
+// are deterministic.
+#include "vtgs_internal.h"
+
+namespace vtgs {
+
+namespace {
+
+constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
+
+template <int TILE>
+struct Shape {
+  static constexpr int NT = TILE == 8 ? 64 : 256;
+  static constexpr int PPT = TILE * TILE / NT;  // pixels per lane
+  static constexpr int WB = TILE == 32 ? 16 : 8;  // side of a wave's block
+};
+
+// Pixel k of this lane, relative to the tile origin.
+template <int TILE>
+__device__ __forceinline__ void lane_pixel(int k, int &x, int &y) {
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  if (TILE == 8) { x = l % 8; y = l / 8; return; }
+  const int qx = (w % 2) * Shape<TILE>::WB, qy = (w / 2) * Shape<TILE>::WB;
+  x = qx + l % 8 + 8 * (k % 2);
+  y = qy + l / 8 + 8 * (k / 2);
+}
+
+template <int TILE>
+__device__ __forceinline__ void wave_block(int &x0, int &y0) {
+  const int w = threadIdx.x / kWave;
+  if (TILE == 8) { x0 = 0; y0 = 0; return; }
+  x0 = (w % 2) * Shape<TILE>::WB;
+  y0 = (w / 2) * Shape<TILE>::WB;
+}
+
+// q = d^T Q d in a fixed order (d = pixel - mu).
+__device__ __forceinline__ float quad(const float4 &e0, float qc, float px, float py, float &dx,
+                                      float &dy) {
+  dx = px - e0.x;
+  dy = py - e0.y;
+  float q = (e0.z * dx) * dx;
+  q = fmaf((2.0f * e0.w) * dx, dy, q);
+  q = fmaf(qc * dy, dy, q);
+  return q;
+}
+
+// Does the extent box mu +- R miss the wave's pixel block?  Scalar branch.
+__device__ __forceinline__ bool wave_skip(const float4 &e0, float R, float bx0, float by0,
+                                          float bx1, float by1) {
+  const bool miss = (e0.x + R < bx0) | (e0.x - R > bx1) | (e0.y + R < by0) | (e0.y - R > by1);
+  return __builtin_amdgcn_readfirstlane((int)miss) != 0;
+}
+
+template <int TILE, int BATCH>
+__global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, float *out_depth,
+                                                         float *out_sil) {
+  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
+  __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
+  const int t = blockIdx.x;
+  const DevView &vw = ws.views[find_view_by_tile(ws, t)];
+  const int lt = t - vw.tile_base;
+  const int ox = (lt % vw.tiles_x) * TILE, oy = (lt / vw.tiles_x) * TILE;
+  int wx0, wy0;
+  wave_block<TILE>(wx0, wy0);
+  const float bx0 = (float)(ox + wx0), by0 = (float)(oy + wy0);
+  const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
+  const uint2 rg = ws.ranges[t];
+  const int start = (int)rg.x, end = (int)rg.y;
+
+  float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
+  uint32_t last[PPT];
+  bool done[PPT], valid[PPT];
+#pragma unroll
+  for (int k = 0; k < PPT; k++) {
+    int x, y;
+    lane_pixel<TILE>(k, x, y);
+    px[k] = (float)(ox + x);
+    py[k] = (float)(oy + y);
+    valid[k] = (ox + x) < vw.width && (oy + y) < vw.height;
+    done[k] = !valid[k];
+    T[k] = 1.f; C0[k] = C1[k] = C2[k] = D[k] = 0.f; last[k] = 0;
+  }
+  const float amin = ws.amin, amax = ws.amax, tmin = ws.tmin, qcut = ws.qcut;
+
+  for (int b = start; b < end; b += BATCH) {
+    bool mine = true;
+#pragma unroll
+    for (int k = 0; k < PPT; k++) mine &= done[k];
+    if (__syncthreads_count(mine) == NT) break;
+    const int nb = min(BATCH, end - b);
+    for (int i = threadIdx.x; i < nb; i += NT) {
+      const uint32_t id = ws.ids[b + i];
+      if (id < (uint32_t)vw.n_rec) {
+        const float4 *A = ws.recA + 3 * ((int64_t)vw.rec_base + id);
+        e0s[i] = A[0]; e1s[i] = A[1]; e2s[i] = A[2];
+      } else {  // never happens for a consistent list; an empty entry is skipped
+        e0s[i] = make_float4(-1e30f, -1e30f, 0.f, 0.f);
+        e1s[i] = make_float4(0.f, 0.f, 1.f, 0.f);
+        e2s[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane((int)(ballot64(!mine) != 0ull)) == 0) continue;
+    for (int j = 0; j < nb; j++) {
+      const float4 e0 = e0s[j];
+      const float4 e1 = e1s[j];
+      if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        if (done[k]) continue;
+        float dx, dy;
+        const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+        if (!(q <= qcut)) continue;
+        const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+        const float a = fminf(amax, e1.y * G);
+        if (!(a >= amin)) continue;
+        const float Tn = T[k] * (1.0f - a);
+        if (Tn < tmin) { done[k] = true; continue; }
+        const float4 e2 = e2s[j];
+        const float wgt = a * T[k];
+        C0[k] = fmaf(e2.x, wgt, C0[k]);
+        C1[k] = fmaf(e2.y, wgt, C1[k]);
+        C2[k] = fmaf(e2.z, wgt, C2[k]);
+        D[k] = fmaf(e1.z, wgt, D[k]);
+        T[k] = Tn;
+        last[k] = (uint32_t)(b - start + j + 1);
+      }
+    }
+  }
+  const int64_t P = ws.P;
+#pragma unroll
+  for (int k = 0; k < PPT; k++) {
+    if (!valid[k]) continue;
+    const int64_t p = vw.pix_off + (int64_t)((int)py[k]) * vw.width + (int)px[k];
+    if (out_rgb) {
+      out_rgb[p] = fmaf(T[k], ws.bg[0], C0[k]);
+      out_rgb[P + p] = fmaf(T[k], ws.bg[1], C1[k]);
+      out_rgb[2 * P + p] = fmaf(T[k], ws.bg[2], C2[k]);
+    }
+    if (out_depth) out_depth[p] = D[k];
+    if (out_sil) out_sil[p] = 1.0f - T[k];
+    ws.t_final[p] = T[k];
+    ws.last[p] = last[k];
+  }
+}
+
+template <int TILE, int BATCH, int MODE>
+__global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_rgb,
+                                                         const float *g_depth,
+                                                         const float *g_sil) {
+  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
+  constexpr int NW = NT / kWave;
+  constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
+  constexpr int AB = kSlots ? BATCH : 1;
+  __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
+  __shared__ float4 ejs[BATCH];   // (fx/z, fy/z, -fx px/z^2, -fy py/z^2)
+  __shared__ float4 eps_[BATCH];  // (px, py, 2 r^2 / z, learnable)
+  __shared__ uint32_t slot_s[AB];
+  __shared__ float acc[NW][5][AB];
+  __shared__ int maxlast_s;
+  __shared__ float red_s[NW][6];
+
+  const int t = blockIdx.x;
+  const DevView &vw = ws.views[find_view_by_tile(ws, t)];
+  const int lt = t - vw.tile_base;
+  const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
+  const int ox = tx * TILE, oy = ty * TILE;
+  int wx0, wy0;
+  wave_block<TILE>(wx0, wy0);
+  const float bx0 = (float)(ox + wx0), by0 = (float)(oy + wy0);
+  const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
+  const uint2 rg = ws.ranges[t];
+  const int start = (int)rg.x, end = (int)rg.y;
+  const int64_t P = ws.P;
+  const int w = threadIdx.x / kWave;
+
+  float px[PPT], py[PPT], T[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gS[PPT];
+  float BC0[PPT], BC1[PPT], BC2[PPT], BD[PPT], BS[PPT];
+  uint32_t last[PPT];
+  uint32_t mylast = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; k++) {
+    int x, y;
+    lane_pixel<TILE>(k, x, y);
+    px[k] = (float)(ox + x);
+    py[k] = (float)(oy + y);
+    const bool valid = (ox + x) < vw.width && (oy + y) < vw.height;
+    const int64_t p = vw.pix_off + (int64_t)(oy + y) * vw.width + (ox + x);
+    T[k] = valid ? ws.t_final[p] : 1.f;
+    last[k] = valid ? ws.last[p] : 0u;
+    gC0[k] = (valid && g_rgb) ? g_rgb[p] : 0.f;
+    gC1[k] = (valid && g_rgb) ? g_rgb[P + p] : 0.f;
+    gC2[k] = (valid && g_rgb) ? g_rgb[2 * P + p] : 0.f;
+    gD[k] = (valid && g_depth) ? g_depth[p] : 0.f;
+    gS[k] = (valid && g_sil) ? g_sil[p] : 0.f;
+    BC0[k] = ws.bg[0]; BC1[k] = ws.bg[1]; BC2[k] = ws.bg[2];
+    BD[k] = 0.f; BS[k] = 0.f;
+    mylast = max(mylast, last[k]);
+  }
+  if (threadIdx.x == 0) maxlast_s = 0;
+  __syncthreads();
+  atomicMax(&maxlast_s, (int)mylast);
+  __syncthreads();
+  const int stop = start + maxlast_s;
+
+  float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const float amin = ws.amin, amax = ws.amax, qcut = ws.qcut;
+  const float vfx = vw.fx, vfy = vw.fy;
+
+  for (int hi = stop; hi > start; hi -= BATCH) {
+    const int lo = max(start, hi - BATCH);
+    const int nb = hi - lo;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += NT) {
+      const uint32_t id = ws.ids[lo + i];
+      const bool ok = id < (uint32_t)vw.n_rec;
+      const int rec = vw.rec_base + (ok ? (int)id : 0);
+      const float4 *A = ws.recA + 3 * (int64_t)rec;
+      float4 e0 = A[0], e1 = A[1], e2 = A[2];
+      float4 eb = ws.recB[rec];
+      if (!ok) {  // never happens for a consistent list; an empty entry is skipped
+        e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
+        e1 = make_float4(0.f, 0.f, 1.f, 0.f);
+        eb.z = 0.f;
+      }
+      e0s[i] = e0; e1s[i] = e1; e2s[i] = e2;
+      const float z = e1.z, iz = 1.0f / z;
+      ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * eb.x * iz * iz, -vfy * eb.y * iz * iz);
+      eps_[i] = make_float4(eb.x, eb.y, 2.0f * e2.w * e2.w * iz, eb.z);
+      if (kSlots) {
+        const uint2 rc = ws.rect[rec];
+        const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
+        const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
+        slot_s[i] = sl;
+        if (!(sl < (uint64_t)ws.cap)) eps_[i].w = 0.f;  // only after a capacity overflow
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++)
+#pragma unroll
+          for (int c = 0; c < 5; c++) acc[ww][c][i] = 0.f;
+      }
+    }
+    __syncthreads();
+    for (int j = nb - 1; j >= 0; j--) {
+      const float4 e0 = e0s[j];
+      const float4 e1 = e1s[j];
+      if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
+      const int idx = lo + j - start;
+      const float4 e2 = e2s[j];
+      const float4 ej = ejs[j];
+      const float4 ep = eps_[j];
+      float sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, so = 0.f, sr = 0.f;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        if (idx >= (int)last[k]) continue;
+        float dx, dy;
+        const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+        if (!(q <= qcut)) continue;
+        const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+        const float oG = e1.y * G;
+        const float a = fminf(amax, oG);
+        if (!(a >= amin)) continue;
+        any = true;
+        const float om = 1.0f - a;
+        T[k] = T[k] * __builtin_amdgcn_rcpf(om);
+        const float wgt = a * T[k];
+        float dLda = gC0[k] * (e2.x - BC0[k]);
+        dLda = fmaf(gC1[k], e2.y - BC1[k], dLda);
+        dLda = fmaf(gC2[k], e2.z - BC2[k], dLda);
+        dLda = fmaf(gD[k], e1.z - BD[k], dLda);
+        dLda = fmaf(gS[k], 1.0f - BS[k], dLda);
+        dLda *= T[k];
+        BC0[k] = fmaf(a, e2.x, om * BC0[k]);
+        BC1[k] = fmaf(a, e2.y, om * BC1[k]);
+        BC2[k] = fmaf(a, e2.z, om * BC2[k]);
+        BD[k] = fmaf(a, e1.z, om * BD[k]);
+        BS[k] = fmaf(a, 1.0f, om * BS[k]);
+        const bool pass = oG <= amax;
+        const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
+        // t = J^T Q d
+        const float qb = e0.w;
+        const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
+        const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
+        if (kTwist) {
+          const float kk = ep.z;
+          const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
+          const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
+          const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
+          const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+          const float pz = e1.z;
+          tw[0] += g0; tw[1] += g1; tw[2] += g2;
+          tw[3] += ep.y * g2 - pz * g1;
+          tw[4] += pz * g0 - ep.x * g2;
+          tw[5] += ep.x * g1 - ep.y * g0;
+        }
+        if (kSlots) {
+          sc0 = fmaf(wgt, gC0[k], sc0);
+          sc1 = fmaf(wgt, gC1[k], sc1);
+          sc2 = fmaf(wgt, gC2[k], sc2);
+          so = pass ? fmaf(G, dLda, so) : so;
+          const float tt = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
+          sr = fmaf(dLdq, -2.0f * e2.w * tt, sr);
+        }
+      }
+      if (kSlots && ep.w != 0.f && ballot64(any) != 0ull) {
+        const float r0 = wave_sum(sc0), r1 = wave_sum(sc1), r2 = wave_sum(sc2);
+        const float r3 = wave_sum(so), r4 = wave_sum(sr);
+        if (lane_id() == 0) {
+          acc[w][0][j] = r0; acc[w][1][j] = r1; acc[w][2][j] = r2;
+          acc[w][3][j] = r3; acc[w][4][j] = r4;
+        }
+      }
+    }
+    if (kSlots) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += NT) {
+        if (eps_[i].w == 0.f) continue;
+        float *o = ws.slots + 5 * (int64_t)slot_s[i];
+#pragma unroll
+        for (int c = 0; c < 5; c++) {
+          float s = 0.f;
+#pragma unroll
+          for (int ww = 0; ww < NW; ww++) s += acc[ww][c][i];
+          o[c] = s;
+        }
+      }
+    }
+  }
+  if (kSlots) {
+    // list entries past every pixel's last contributor: zero slots
+    for (int i = stop + (int)threadIdx.x; i < end; i += NT) {
+      const uint32_t id = ws.ids[i];
+      if (!(id < (uint32_t)vw.n_rec)) continue;
+      const int rec = vw.rec_base + (int)id;
+      const uint2 rc = ws.rect[rec];
+      const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
+      const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
+      if (!(sl < (uint64_t)ws.cap)) continue;
+      float *o = ws.slots + 5 * (int64_t)sl;
+#pragma unroll
+      for (int c = 0; c < 5; c++) o[c] = 0.f;
+    }
+  }
+  if (kTwist) {
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+      const float s = wave_sum(tw[c]);
+      if (lane_id() == 0) red_s[w][c] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      float s = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < NW; ww++) s += red_s[ww][threadIdx.x];
+      ws.twist_part[6 * (int64_t)t + threadIdx.x] = s;
+    }
+  }
+}
+
+template <int TILE, int BATCH>
+hipError_t fwd_launch(const Ws &ws, float *rgb, float *depth, float *sil, hipStream_t st) {
+  hipLaunchKernelGGL((k_fwd<TILE, BATCH>), dim3(ws.n_tiles), dim3(Shape<TILE>::NT), 0, st, ws,
+                     rgb, depth, sil);
+  return hipGetLastError();
+}
+
+template <int TILE, int BATCH>
+hipError_t bwd_launch(const Ws &ws, const float *g_rgb, const float *g_depth, const float *g_sil,
+                      int mode, hipStream_t st) {
+  const dim3 g(ws.n_tiles), b(Shape<TILE>::NT);
+  switch (mode) {
+    case 1: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 1>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
+    case 2: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 2>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
+    case 3: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 3>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int TILE>
+hipError_t fwd_tile(const Ws &ws, float *rgb, float *depth, float *sil, hipStream_t st) {
+  switch (ws.batch) {
+    case 128: return fwd_launch<TILE, 128>(ws, rgb, depth, sil, st);
+    case 256: return fwd_launch<TILE, 256>(ws, rgb, depth, sil, st);
+    case 512: return fwd_launch<TILE, 512>(ws, rgb, depth, sil, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int TILE>
+hipError_t bwd_tile(const Ws &ws, const float *a, const float *b, const float *c, int mode,
+                    hipStream_t st) {
+  switch (ws.batch) {
+    case 128: return bwd_launch<TILE, 128>(ws, a, b, c, mode, st);
+    case 256: return bwd_launch<TILE, 256>(ws, a, b, c, mode, st);
+    case 512: return bwd_launch<TILE, 512>(ws, a, b, c, mode, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_composite_fwd(const Ws &ws, float *rgb, float *depth, float *sil,
+                                hipStream_t st) {
+  if (ws.n_tiles == 0) return hipSuccess;
+  switch (ws.tile) {
+    case 8: return fwd_tile<8>(ws, rgb, depth, sil, st);
+    case 16: return fwd_tile<16>(ws, rgb, depth, sil, st);
+    case 32: return fwd_tile<32>(ws, rgb, depth, sil, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_composite_bwd(const Ws &ws, const float *g_rgb, const float *g_depth,
+                                const float *g_sil, int mode, hipStream_t st) {
+  if (ws.n_tiles == 0) return hipSuccess;
+  switch (ws.tile) {
+    case 8: return bwd_tile<8>(ws, g_rgb, g_depth, g_sil, mode, st);
+    case 16: return bwd_tile<16>(ws, g_rgb, g_depth, g_sil, mode, st);
+    case 32: return bwd_tile<32>(ws, g_rgb, g_depth, g_sil, mode, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace vtgs

@@ -1,0 +1,438 @@
+// Losses and optimiser steps around the splat.
+//
+//  track_loss   Eq. 1 (Sec. 3.3): alpha sum W |V - V'| + beta sum W |D - D'|
+//               with W = vis & (D > 0) & (S' > sil_thr) held fixed; writes
+//               dL/dV', dL/dD' and per-block loss sums
+//  twist_reduce per view, the tiles' twist partials summed in a fixed order
+//  track_update twist reduce + Adam on the twist (lr_trans on rho, lr_rot on
+//               phi; App. A) + pose <- exp(step^) pose
+//  map_l1       Eq. 2 (Sec. 3.4) L1 terms: rho mean|V - V'|,
+//               sigma mean(U |D - D'|) with U = (D > 0); gradients
+//  ssim_a/b     tau (1 - SSIM(V, V')): 11x11 Gaussian window (sigma 1.5),
+//               zero padding, C1 = 0.01^2, C2 = 0.03^2; separable passes
+//               through LDS; the backward filters the per-pixel partials
+//               with the same (symmetric) window
+//  gather       per learnable keyframe Gaussian, the (record, tile) slots of
+//               every view that renders it, summed in a fixed order; then
+//               either added to the caller's gradient planes or used for
+//               one Adam step on (c, logit o, log r) (App. A learning rates)
+#include "vtgs_internal.h"
+
+namespace vtgs {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
+
+__device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
+
+__device__ __forceinline__ float block_sum(float x, float *lds) {
+  const float s = wave_sum(x);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) lds[w] = s;
+  __syncthreads();
+  float t = 0.f;
+  for (int i = 0; i < (int)(blockDim.x / kWave); i++) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kNT) void k_track_loss(Ws ws, vtgs_track_cfg cfg) {
+  __shared__ float lds[kNT / kWave];
+  const int v = blockIdx.y;
+  const DevView &vw = ws.views[v];
+  const int64_t Pv = (int64_t)vw.width * vw.height;
+  const int64_t lp = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const int64_t P = ws.P;
+  float l = 0.f;
+  if (lp < Pv) {
+    const int64_t p = vw.pix_off + lp;
+    const float od = vw.obs_depth[lp];
+    const bool W = (!vw.vis || vw.vis[lp] != 0) && od > 0.f && ws.img[4 * P + p] > cfg.sil_thr;
+    for (int c = 0; c < 3; c++) {
+      const float r = vw.obs_rgb[c * Pv + lp] - ws.img[c * P + p];
+      if (W) l += cfg.alpha * fabsf(r);
+      ws.gimg[c * P + p] = W ? -cfg.alpha * sgnf(r) : 0.f;
+    }
+    const float rd = od - ws.img[3 * P + p];
+    if (W) l += cfg.beta * fabsf(rd);
+    ws.gimg[3 * P + p] = W ? -cfg.beta * sgnf(rd) : 0.f;
+  }
+  const float s = block_sum(l, lds);
+  if (threadIdx.x == 0) ws.loss_part[4 * ((int64_t)v * ws.loss_blocks + blockIdx.x)] = s;
+}
+
+// Sum of the view's tile partials (6 floats each) and loss partials.
+__device__ __forceinline__ void reduce_view(const Ws &ws, int v, float *g6, float *loss,
+                                           float *lds) {
+  const DevView &vw = ws.views[v];
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int i = threadIdx.x; i < vw.n_tiles; i += blockDim.x)
+    for (int c = 0; c < 6; c++) acc[c] += ws.twist_part[6 * (int64_t)(vw.tile_base + i) + c];
+  for (int c = 0; c < 6; c++) g6[c] = block_sum(acc[c], lds);
+  if (loss) {
+    const int nb = (int)((((int64_t)vw.width * vw.height) + kNT - 1) / kNT);
+    float l = 0.f;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+      l += ws.loss_part[4 * ((int64_t)v * ws.loss_blocks + i)];
+    *loss = block_sum(l, lds);
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_twist_reduce(Ws ws, float *g_twist) {
+  __shared__ float lds[kNT / kWave];
+  float g[6];
+  reduce_view(ws, blockIdx.x, g, nullptr, lds);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 6; c++) g_twist[6 * blockIdx.x + c] = g[c];
+}
+
+// exp of a twist (rho, phi): R = I + A K + B K^2, t = (I + B K + C K^2) rho.
+__device__ void se3_exp(const float *xi, float *E) {
+  const float *rho = xi, *phi = xi + 3;
+  const float th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+  const float th = sqrtf(th2);
+  float A, B, C;
+  if (th < 1e-3f) {
+    A = 1.f - th2 / 6.f;
+    B = 0.5f - th2 / 24.f;
+    C = 1.f / 6.f - th2 / 120.f;
+  } else {
+    A = sinf(th) / th;
+    B = (1.f - cosf(th)) / th2;
+    C = (th - sinf(th)) / (th2 * th);
+  }
+  const float K[3][3] = {{0.f, -phi[2], phi[1]}, {phi[2], 0.f, -phi[0]}, {-phi[1], phi[0], 0.f}};
+  float K2[3][3];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) K2[i][j] = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+  for (int i = 0; i < 3; i++) {
+    float t = 0.f;
+    for (int j = 0; j < 3; j++) {
+      const float I = i == j ? 1.f : 0.f;
+      E[4 * i + j] = I + A * K[i][j] + B * K2[i][j];
+      t += (I + B * K[i][j] + C * K2[i][j]) * rho[j];
+    }
+    E[4 * i + 3] = t;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_track_update(Ws ws, vtgs_track_cfg cfg, float *loss) {
+  __shared__ float lds[kNT / kWave];
+  const int v = blockIdx.x;
+  float g[6], L;
+  reduce_view(ws, v, g, &L, lds);
+  if (threadIdx.x != 0) return;
+  const DevView &vw = ws.views[v];
+  if (loss) loss[v] = L;
+  bool finite = __builtin_isfinite(L);
+  for (int c = 0; c < 6; c++) finite &= __builtin_isfinite(g[c]);
+  if (!finite) { atomicOr(ws.flags, kFlagNonfinite); return; }
+  float *st = vw.pose_adam;
+  const float t = st[12] + 1.f;
+  st[12] = t;
+  const float c1 = 1.f - powf(kB1, t), c2 = 1.f - powf(kB2, t);
+  float xi[6];
+  for (int i = 0; i < 6; i++) {
+    const float m = kB1 * st[i] + (1.f - kB1) * g[i];
+    const float s = kB2 * st[6 + i] + (1.f - kB2) * g[i] * g[i];
+    st[i] = m;
+    st[6 + i] = s;
+    const float lr = i < 3 ? cfg.lr_trans : cfg.lr_rot;
+    xi[i] = -lr * (m / c1) / (sqrtf(s / c2) + kEps);
+  }
+  float E[12], T[12], N[12];
+  se3_exp(xi, E);
+  for (int i = 0; i < 12; i++) T[i] = vw.pose[i];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 4; j++) {
+      float s = E[4 * i + 0] * T[j] + E[4 * i + 1] * T[4 + j] + E[4 * i + 2] * T[8 + j];
+      if (j == 3) s += E[4 * i + 3];
+      N[4 * i + j] = s;
+    }
+  for (int i = 0; i < 12; i++) vw.pose[i] = N[i];
+}
+
+// ---- Eq. 2 ----------------------------------------------------------------
+
+__global__ __launch_bounds__(kNT) void k_map_l1(Ws ws, vtgs_map_cfg cfg) {
+  __shared__ float lds[kNT / kWave];
+  const int v = blockIdx.y;
+  const DevView &vw = ws.views[v];
+  const int64_t Pv = (int64_t)vw.width * vw.height;
+  const int64_t lp = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const int64_t P = ws.P;
+  float l1 = 0.f, ld = 0.f;
+  if (lp < Pv) {
+    const int64_t p = vw.pix_off + lp;
+    const float inv3 = 1.0f / (3.0f * (float)Pv), inv1 = 1.0f / (float)Pv;
+    for (int c = 0; c < 3; c++) {
+      const float r = vw.obs_rgb[c * Pv + lp] - ws.img[c * P + p];
+      l1 += fabsf(r);
+      ws.gimg[c * P + p] = -cfg.rho * sgnf(r) * inv3;
+    }
+    const float od = vw.obs_depth[lp];
+    const float rd = od - ws.img[3 * P + p];
+    const bool U = od > 0.f;
+    if (U) ld += fabsf(rd);
+    ws.gimg[3 * P + p] = U ? -cfg.sigma * sgnf(rd) * inv1 : 0.f;
+  }
+  const float s1 = block_sum(l1, lds);
+  const float s2 = block_sum(ld, lds);
+  if (threadIdx.x == 0) {
+    float *o = ws.loss_part + 4 * ((int64_t)v * ws.loss_blocks + blockIdx.x);
+    o[0] = s1;
+    o[1] = s2;
+  }
+}
+
+constexpr int kS = 16, kR = 5, kH = kS + 2 * kR;  // SSIM output tile, window radius
+
+__device__ __forceinline__ float gwin(int k) {
+  // normalised 11-tap Gaussian, sigma 1.5
+  constexpr float w[11] = {1.028380124e-03f, 7.598758209e-03f, 3.600077331e-02f,
+                           1.093606874e-01f, 2.130055428e-01f, 2.660117149e-01f,
+                           2.130055428e-01f, 1.093606874e-01f, 3.600077331e-02f,
+                           7.598758209e-03f, 1.028380124e-03f};
+  return w[k];
+}
+
+__global__ __launch_bounds__(kNT) void k_ssim_a(Ws ws, int gx, int gy) {
+  __shared__ float xs[kH][kH], ys[kH][kH];
+  __shared__ float hs[5][kH][kS];
+  __shared__ float lds[kNT / kWave];
+  const int v = blockIdx.z / 3, c = blockIdx.z % 3;
+  const DevView &vw = ws.views[v];
+  const int W = vw.width, H = vw.height;
+  const int x0 = blockIdx.x * kS, y0 = blockIdx.y * kS;
+  if (x0 >= W || y0 >= H) {
+    if (threadIdx.x == 0) ws.ssim_part[((int64_t)blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x] = 0.f;
+    return;
+  }
+  const int64_t P = ws.P, Pv = (int64_t)W * H;
+  const float *X = ws.img + c * P + vw.pix_off;
+  const float *Y = vw.obs_rgb + c * Pv;
+  for (int i = threadIdx.x; i < kH * kH; i += kNT) {
+    const int yy = y0 - kR + i / kH, xx = x0 - kR + i % kH;
+    const bool in = xx >= 0 && xx < W && yy >= 0 && yy < H;
+    xs[i / kH][i % kH] = in ? X[(int64_t)yy * W + xx] : 0.f;
+    ys[i / kH][i % kH] = in ? Y[(int64_t)yy * W + xx] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kH * kS; i += kNT) {
+    const int r = i / kS, cc = i % kS;
+    float a = 0.f, b = 0.f, aa = 0.f, bb = 0.f, ab = 0.f;
+    for (int k = 0; k < 2 * kR + 1; k++) {
+      const float w = gwin(k), xv = xs[r][cc + k], yv = ys[r][cc + k];
+      a = fmaf(w, xv, a); b = fmaf(w, yv, b);
+      aa = fmaf(w, xv * xv, aa); bb = fmaf(w, yv * yv, bb); ab = fmaf(w, xv * yv, ab);
+    }
+    hs[0][r][cc] = a; hs[1][r][cc] = b; hs[2][r][cc] = aa; hs[3][r][cc] = bb; hs[4][r][cc] = ab;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kS, ly = threadIdx.x / kS;
+  const int xx = x0 + lx, yy = y0 + ly;
+  float S = 0.f;
+  if (xx < W && yy < H) {
+    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 2 * kR + 1; k++) {
+      const float w = gwin(k);
+      for (int q = 0; q < 5; q++) m[q] = fmaf(w, hs[q][ly + k][lx], m[q]);
+    }
+    const float C1 = 1e-4f, C2 = 9e-4f;
+    const float mx = m[0], my = m[1];
+    const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
+    const float A1 = 2.f * mx * my + C1, A2 = 2.f * cxy + C2;
+    const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
+    const float inv = 1.f / (B1 * B2);
+    S = A1 * A2 * inv;
+    const float Smu = 2.f * my * A2 * inv - 2.f * mx * S / B1;
+    const float Ssig = -S / B2;
+    const float Scov = 2.f * A1 * inv;
+    const int64_t p = (int64_t)c * P + vw.pix_off + (int64_t)yy * W + xx;
+    ws.ssim_map[p] = Smu - 2.f * mx * Ssig - my * Scov;
+    ws.ssim_map[3 * P + p] = Ssig;
+    ws.ssim_map[6 * P + p] = Scov;
+  }
+  const float s = block_sum(S, lds);
+  if (threadIdx.x == 0) ws.ssim_part[((int64_t)blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x] = s;
+}
+
+// dSSIM_mean/dx(p) = (1/P) [ (w*A)(p) + 2 x(p) (w*B)(p) + y(p) (w*Cov)(p) ]
+__global__ __launch_bounds__(kNT) void k_ssim_b(Ws ws, vtgs_map_cfg cfg) {
+  __shared__ float ms[3][kH][kH];
+  __shared__ float hs[3][kH][kS];
+  const int v = blockIdx.z / 3, c = blockIdx.z % 3;
+  const DevView &vw = ws.views[v];
+  const int W = vw.width, H = vw.height;
+  const int x0 = blockIdx.x * kS, y0 = blockIdx.y * kS;
+  if (x0 >= W || y0 >= H) return;
+  const int64_t P = ws.P, Pv = (int64_t)W * H;
+  for (int i = threadIdx.x; i < kH * kH; i += kNT) {
+    const int yy = y0 - kR + i / kH, xx = x0 - kR + i % kH;
+    const bool in = xx >= 0 && xx < W && yy >= 0 && yy < H;
+    const int64_t p = (int64_t)c * P + vw.pix_off + (int64_t)yy * W + xx;
+    for (int q = 0; q < 3; q++) ms[q][i / kH][i % kH] = in ? ws.ssim_map[q * 3 * P + p] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kH * kS; i += kNT) {
+    const int r = i / kS, cc = i % kS;
+    float a[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 2 * kR + 1; k++) {
+      const float w = gwin(k);
+      for (int q = 0; q < 3; q++) a[q] = fmaf(w, ms[q][r][cc + k], a[q]);
+    }
+    for (int q = 0; q < 3; q++) hs[q][r][cc] = a[q];
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kS, ly = threadIdx.x / kS;
+  const int xx = x0 + lx, yy = y0 + ly;
+  if (xx >= W || yy >= H) return;
+  float f[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < 2 * kR + 1; k++) {
+    const float w = gwin(k);
+    for (int q = 0; q < 3; q++) f[q] = fmaf(w, hs[q][ly + k][lx], f[q]);
+  }
+  const int64_t lp = (int64_t)yy * W + xx;
+  const int64_t p = vw.pix_off + lp;
+  const float x = ws.img[c * P + p], y = vw.obs_rgb[c * Pv + lp];
+  const float g = (f[0] + 2.f * x * f[1] + y * f[2]) / (float)Pv;
+  ws.gimg[c * P + p] += -cfg.tau * g / 3.f;
+}
+
+__global__ __launch_bounds__(kNT) void k_map_loss_reduce(Ws ws, vtgs_map_cfg cfg, int gx, int gy,
+                                                         float *loss) {
+  __shared__ float lds[kNT / kWave];
+  const int v = blockIdx.x;
+  const DevView &vw = ws.views[v];
+  const int64_t Pv = (int64_t)vw.width * vw.height;
+  const int nb = (int)((Pv + kNT - 1) / kNT);
+  float a = 0.f, b = 0.f, s = 0.f;
+  for (int i = threadIdx.x; i < nb; i += kNT) {
+    const float *o = ws.loss_part + 4 * ((int64_t)v * ws.loss_blocks + i);
+    a += o[0];
+    b += o[1];
+  }
+  for (int i = threadIdx.x; i < 3 * gx * gy; i += kNT) s += ws.ssim_part[(int64_t)v * 3 * gx * gy + i];
+  a = block_sum(a, lds);
+  b = block_sum(b, lds);
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    const float L = cfg.rho * a / (3.f * (float)Pv) + cfg.tau * (1.f - s / (3.f * (float)Pv)) +
+                    cfg.sigma * b / (float)Pv;
+    if (!__builtin_isfinite(L)) atomicOr(ws.flags, kFlagNonfinite);
+    if (loss) loss[v] = L;
+  }
+}
+
+// Sum of a keyframe Gaussian's slots over the views rendering it.
+__device__ __forceinline__ void gather5(const Ws &ws, int kf, int i, float *g) {
+  for (int c = 0; c < 5; c++) g[c] = 0.f;
+  for (int u = ws.kf_use_off[kf]; u < ws.kf_use_off[kf + 1]; u++) {
+    const int rec = ws.kf_use[u].rec_start + i;
+    const uint32_t a = ws.rec_off[rec];
+    const uint32_t b = (uint64_t)ws.rec_off[rec + 1] < (uint64_t)ws.cap ? ws.rec_off[rec + 1]
+                                                                        : (uint32_t)ws.cap;
+    for (uint32_t s = a; s < b; s++)
+      for (int c = 0; c < 5; c++) g[c] += ws.slots[5 * (int64_t)s + c];
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_gather_accumulate(Ws ws) {
+  const int kf = blockIdx.y;
+  const DevKF &K = ws.kfs[kf];
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (!K.learnable || i >= K.n) return;
+  float g[5];
+  gather5(ws, kf, i, g);
+  if (K.g_color)
+    for (int c = 0; c < 3; c++) K.g_color[(int64_t)c * K.n + i] += g[c];
+  if (K.g_opacity) K.g_opacity[i] += g[3];
+  if (K.g_radius) K.g_radius[i] += g[4];
+}
+
+__global__ __launch_bounds__(kNT) void k_map_adam(Ws ws, vtgs_map_cfg cfg, const int32_t *step) {
+  const int kf = blockIdx.y;
+  const DevKF &K = ws.kfs[kf];
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (!K.learnable || !K.adam || i >= K.n) return;
+  float g[5];
+  gather5(ws, kf, i, g);
+  const float t = (float)(*step);
+  const float c1 = 1.f - powf(kB1, t), c2 = 1.f - powf(kB2, t);
+  const int64_t n = K.n;
+  const float o = K.opacity[i], r = K.radius[i];
+  // parameters: colour as is, logit of opacity, log of radius
+  float x[5] = {K.color[i], K.color[n + i], K.color[2 * n + i], logf(o / (1.f - o)), logf(r)};
+  const float gx[5] = {g[0], g[1], g[2], g[3] * o * (1.f - o), g[4] * r};
+  const float lr[5] = {cfg.lr_color, cfg.lr_color, cfg.lr_color, cfg.lr_opacity, cfg.lr_radius};
+  float *M = K.adam, *V = K.adam + 5 * n;
+  for (int c = 0; c < 5; c++) {
+    const float m = kB1 * M[c * n + i] + (1.f - kB1) * gx[c];
+    const float s = kB2 * V[c * n + i] + (1.f - kB2) * gx[c] * gx[c];
+    M[c * n + i] = m;
+    V[c * n + i] = s;
+    x[c] -= lr[c] * (m / c1) / (sqrtf(s / c2) + kEps);
+  }
+  K.color[i] = x[0];
+  K.color[n + i] = x[1];
+  K.color[2 * n + i] = x[2];
+  K.opacity[i] = 1.f / (1.f + expf(-x[3]));
+  K.radius[i] = expf(x[4]);
+}
+
+__global__ void k_step_inc(int32_t *step) { *step += 1; }
+
+}  // namespace
+
+hipError_t launch_track_loss(const Ws &ws, const vtgs_track_cfg &cfg, hipStream_t st) {
+  hipLaunchKernelGGL(k_track_loss, dim3(ws.loss_blocks, ws.n_views), dim3(kNT), 0, st, ws, cfg);
+  return hipGetLastError();
+}
+
+hipError_t launch_twist_reduce(const Ws &ws, float *g_twist, hipStream_t st) {
+  hipLaunchKernelGGL(k_twist_reduce, dim3(ws.n_views), dim3(kNT), 0, st, ws, g_twist);
+  return hipGetLastError();
+}
+
+hipError_t launch_track_update(const Ws &ws, const vtgs_track_cfg &cfg, float *loss,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_track_update, dim3(ws.n_views), dim3(kNT), 0, st, ws, cfg, loss);
+  return hipGetLastError();
+}
+
+void ssim_grid(const Ws &ws, int *gx, int *gy) {
+  *gx = ws.ssim_gx;
+  *gy = ws.ssim_gy;
+}
+
+hipError_t launch_map_loss(const Ws &ws, const vtgs_map_cfg &cfg, hipStream_t st) {
+  int gx, gy;
+  ssim_grid(ws, &gx, &gy);
+  hipLaunchKernelGGL(k_map_l1, dim3(ws.loss_blocks, ws.n_views), dim3(kNT), 0, st, ws, cfg);
+  hipLaunchKernelGGL(k_ssim_a, dim3(gx, gy, 3 * ws.n_views), dim3(kNT), 0, st, ws, gx, gy);
+  hipLaunchKernelGGL(k_ssim_b, dim3(gx, gy, 3 * ws.n_views), dim3(kNT), 0, st, ws, cfg);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const Ws &ws, int max_n, hipStream_t st) {
+  if (max_n <= 0 || ws.n_kf == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_accumulate, dim3((max_n + kNT - 1) / kNT, ws.n_kf), dim3(kNT), 0, st,
+                     ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_update(const Ws &ws, const vtgs_map_cfg &cfg, int32_t *step, float *loss,
+                               int max_n, hipStream_t st) {
+  int gx, gy;
+  ssim_grid(ws, &gx, &gy);
+  hipLaunchKernelGGL(k_map_loss_reduce, dim3(ws.n_views), dim3(kNT), 0, st, ws, cfg, gx, gy, loss);
+  hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(1), 0, st, step);
+  if (max_n > 0 && ws.n_kf > 0)
+    hipLaunchKernelGGL(k_map_adam, dim3((max_n + kNT - 1) / kNT, ws.n_kf), dim3(kNT), 0, st, ws,
+                       cfg, (const int32_t *)step);
+  return hipGetLastError();
+}
+
+}  // namespace vtgs

@@ -1,0 +1,405 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: ingestion, preprocessing records and tile lists bit-exact; images
+within 1e-5 absolute on pixels the oracle does not flag as marginal;
+gradients |g - g_ref| <= 1e-3 max(|g_ref|, 1e-4 max|g_ref|) against the FP64
+oracle gradient, with the upstream gradient zeroed at marginal pixels.
+
+Marginal: q is evaluated in the same FP32 operation order on both sides (bit
+identical), but exp is not: the GPU's exp2 with a rounded argument is within
+about 5e-7 relative of the correctly rounded value for q <= q_cut.  The
+oracle flags a pixel when an alpha lies within MARGIN = 2e-6 (relative) of
+alpha_min, or when a stop decision lies closer to t_min than the
+transmittance uncertainty that such alpha errors accumulate (amplified by
+alpha / (1 - alpha) near the 0.99 clamp).  Flagged pixels must stay rare.
+"""
+import numpy as np
+import pytest
+
+from scenes import oracle_kf, room_frames
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+MARGIN = 2e-6
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    torch.cuda.set_device(0)
+    from paper_2506_02741_amd import render
+    return render
+
+
+def T(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_kf(R, fr, stride=1, mask=None, learnable=False):
+    return R.Keyframe.ingest(fr.depth, fr.rgb, fr.cam.as_tuple(), fr.pose, stride, 0.99, mask,
+                             learnable)
+
+
+def grad_close(g, ref, rel=1e-3):
+    g, ref = np.asarray(g, np.float64), np.asarray(ref, np.float64)
+    scale = np.abs(ref).max() if ref.size else 0.0
+    bound = rel * np.maximum(np.abs(ref), 1e-4 * scale)
+    bad = np.abs(g - ref) > bound
+    return not bad.any(), (np.abs(g - ref) / np.maximum(bound, 1e-30)).max() if ref.size else 0.0
+
+
+def check_images(rgb, depth, sil, ref, max_marginal=5e-3):
+    good = ~ref["marginal"]
+    assert good.mean() >= 1 - max_marginal, good.mean()
+    e = [np.abs(np_(rgb) - ref["rgb"])[:, good].max(), np.abs(np_(depth) - ref["depth"])[good].max(),
+         np.abs(np_(sil) - ref["sil"])[good].max()]
+    assert max(e) <= IMG_TOL, e
+    return good
+
+
+# ----------------------------------------------------------------------------
+# a0 ingestion
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("stride", [1, 2, 3])
+@pytest.mark.parametrize("masked", [False, True])
+def test_ingest_bitwise(R, orc, stride, masked):
+    cam, frames, _ = room_frames(21, 83, 61)
+    fr = frames[0]
+    depth = fr.depth.copy()
+    depth[::7, ::5] = 0.0   # holes
+    rng = np.random.default_rng(stride)
+    mask = (rng.uniform(size=depth.shape) < 0.7).astype(np.uint8) if masked else None
+    k = R.Keyframe.ingest(depth, fr.rgb, cam.as_tuple(), fr.pose, stride, 0.8, mask)
+    ref = orc.ingest(depth, fr.rgb, mask, stride, fx=cam.fx, o_init=0.8)
+    assert k.n == ref["pix"].shape[0]
+    assert np.array_equal(np_(k.pix).astype(np.uint32), ref["pix"])
+    for a, b in ((k.depth, ref["depth"]), (k.color, ref["color"]), (k.opacity, ref["opacity"]),
+                 (k.radius, ref["radius"])):
+        assert np.array_equal(np_(a), b)
+
+
+# ----------------------------------------------------------------------------
+# a1-a5 preprocessing records and tile lists
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_records_and_tile_lists_bitwise(R, orc, tile):
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr)
+    plan = R.Plan([k], [R.View(cam.as_tuple(), vpose)], R.params(tile=tile))
+    plan.render_fwd()
+    st = plan.debug_state()
+    rc, need = plan.status()
+    assert rc == 0
+    okf = oracle_kf(orc, fr)
+    ov = orc.ViewSpec(cam.as_tuple(), vpose)
+    prm = orc.params(tile=tile)
+    rec = orc.preprocess32(ov, [okf], prm)
+    g = np_(st["records"])
+    rect = np_(st["rect"])
+    valid = rec["count"] > 0
+    assert np.array_equal(rect[:, 0] <= rect[:, 2], valid)
+    assert np.array_equal(rect[valid], rec["rect"][valid])
+    for col, name in ((0, "mx"), (1, "my"), (2, "qa"), (3, "qb"), (4, "qc"), (6, "pz"), (7, "ext")):
+        assert np.array_equal(g[valid, col], rec[name][valid]), name
+    keys, vals, ranges = orc.tile_lists(ov, [okf], prm)
+    assert int(np_(st["n_pairs"])[0]) == len(vals) == need
+    assert np.array_equal(np_(st["ranges"]).astype(np.uint32), ranges)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+
+
+# ----------------------------------------------------------------------------
+# a6 forward
+# ----------------------------------------------------------------------------
+
+def test_forward_toy_scene(R, orc):
+    from paper_2506_02741_amd import synth
+    f, colors = synth.toy_scene(0)
+    cam = f.cam.as_tuple()
+    k = R.Keyframe.ingest(f.depth, colors, cam, f.pose)
+    plan = R.Plan([k], [R.View(cam, f.pose)])
+    rgb, depth, sil = plan.render_fwd()
+    okf = orc.ingest(f.depth, colors, fx=f.cam.fx, cam=cam, pose=f.pose)
+    ref = orc.render(orc.ViewSpec(cam, f.pose), [okf], margin=MARGIN)
+    check_images(rgb, depth, sil, ref)
+
+
+@pytest.mark.parametrize("tile,batch", [(16, 256), (8, 128), (8, 512), (16, 128), (16, 512),
+                                        (32, 128), (32, 256), (32, 512), (8, 256)])
+def test_forward_room_all_configs_bitwise_equal(R, orc, tile, batch):
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr)
+    view = R.View(cam.as_tuple(), vpose)
+    imgs = R.Plan([k], [view], R.params(tile=tile, batch=batch)).render_fwd()
+    base = R.Plan([k], [view], R.params(tile=16, batch=256)).render_fwd()
+    for a, b in zip(imgs, base):
+        assert np.array_equal(np_(a), np_(b))
+    ref = orc.render(orc.ViewSpec(cam.as_tuple(), vpose), [oracle_kf(orc, fr)], margin=MARGIN)
+    check_images(*imgs, ref)
+
+
+def test_forward_section_multi_keyframe(R, orc):
+    cam, frames, vpose = room_frames(9, 96, 72, n_kf=3)
+    ks = [gpu_kf(R, fr) for fr in frames]
+    plan = R.Plan(ks, [R.View(cam.as_tuple(), vpose, 0, 3)])
+    imgs = plan.render_fwd()
+    ref = orc.render(orc.ViewSpec(cam.as_tuple(), vpose, 0, 3), [oracle_kf(orc, f) for f in frames],
+                     margin=MARGIN)
+    check_images(*imgs, ref)
+
+
+def test_forward_full_size_tracking_frame(R, orc):
+    """640x480, 307,200 Gaussians, perturbed pose: every pixel vs the oracle."""
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1)
+    kf = w["keyframe"]
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, kf.cam.as_tuple(), kf.pose)
+    assert k.n == 640 * 480
+    plan = R.Plan([k], [R.View(kf.cam.as_tuple(), w["init_pose"])])
+    imgs = plan.render_fwd()
+    assert plan.status()[0] == 0
+    ref = orc.render(orc.ViewSpec(kf.cam.as_tuple(), w["init_pose"]),
+                     [oracle_kf(orc, kf)], margin=MARGIN)
+    check_images(*imgs, ref)
+
+
+# ----------------------------------------------------------------------------
+# a9/a10 backward
+# ----------------------------------------------------------------------------
+
+def _random_upstream(P, marginal, seed=0):
+    rng = np.random.default_rng(seed)
+    g_rgb = rng.normal(size=(3, P)); g_d = rng.normal(size=P); g_s = rng.normal(size=P)
+    g_rgb[:, marginal] = 0; g_d[marginal] = 0; g_s[marginal] = 0
+    return g_rgb, g_d, g_s
+
+
+@pytest.mark.parametrize("tile,batch", [(16, 256), (8, 128), (32, 512)])
+def test_backward_parity(R, orc, tile, batch):
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr, learnable=True).with_grad_buffers()
+    plan = R.Plan([k], [R.View(cam.as_tuple(), vpose)], R.params(tile=tile, batch=batch))
+    plan.render_fwd()
+    okf = oracle_kf(orc, fr)
+    ov = orc.ViewSpec(cam.as_tuple(), vpose)
+    ref = orc.render(ov, [okf], margin=MARGIN)
+    g_rgb, g_d, g_s = _random_upstream(plan.P, ref["marginal"])
+    tw = plan.render_bwd(T(g_rgb), T(g_d), T(g_s))
+    gref = orc.render_bwd(ov, [okf], g_rgb, g_d, g_s)
+    for got, name in ((k.g_color, "color"), (k.g_opacity, "opacity"), (k.g_radius, "radius")):
+        ok, worst = grad_close(np_(got), gref[name])
+        assert ok, (name, worst)
+    ok, worst = grad_close(np_(tw)[0], gref["twist"])
+    assert ok, ("twist", worst, np_(tw)[0], gref["twist"])
+
+
+def test_backward_full_size_twist(R, orc):
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1)
+    kf = w["keyframe"]
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, kf.cam.as_tuple(), kf.pose)
+    plan = R.Plan([k], [R.View(kf.cam.as_tuple(), w["init_pose"])])
+    plan.render_fwd()
+    ov = orc.ViewSpec(kf.cam.as_tuple(), w["init_pose"])
+    okf = oracle_kf(orc, kf)
+    ref = orc.render(ov, [okf], margin=MARGIN)
+    L, g_rgb, g_d = orc.track_loss(ref["rgb"], ref["depth"], ref["sil"], kf.rgb, kf.depth)
+    g_rgb[:, ref["marginal"]] = 0; g_d[ref["marginal"]] = 0
+    tw = plan.render_bwd(T(g_rgb), T(g_d), None)
+    gref = orc.render_bwd(ov, [okf], g_rgb, g_d, None)
+    ok, worst = grad_close(np_(tw)[0], gref["twist"])
+    assert ok, (worst, np_(tw)[0], gref["twist"])
+
+
+def test_backward_frozen_keyframe_gets_nothing(R, orc):
+    cam, frames, vpose = room_frames(9, 64, 48, n_kf=2)
+    a = gpu_kf(R, frames[0], learnable=True).with_grad_buffers()
+    b = gpu_kf(R, frames[1], learnable=False).with_grad_buffers()
+    plan = R.Plan([a, b], [R.View(cam.as_tuple(), vpose, 0, 2)])
+    plan.render_fwd()
+    P = plan.P
+    ref = orc.render(orc.ViewSpec(cam.as_tuple(), vpose, 0, 2),
+                     [oracle_kf(orc, f) for f in frames], margin=MARGIN)
+    g_rgb, g_d, g_s = _random_upstream(P, ref["marginal"], 3)
+    plan.render_bwd(T(g_rgb), T(g_d), T(g_s), twist=False)
+    assert float(b.g_color.abs().max()) == 0.0 and float(b.g_radius.abs().max()) == 0.0
+    gref = orc.render_bwd(orc.ViewSpec(cam.as_tuple(), vpose, 0, 2),
+                          [oracle_kf(orc, f) for f in frames], g_rgb, g_d, g_s)
+    n = a.n
+    for got, name in ((a.g_color, "color"), (a.g_opacity, "opacity"), (a.g_radius, "radius")):
+        r = gref[name][..., :n]
+        ok, worst = grad_close(np_(got), r)
+        assert ok, (name, worst)
+
+
+# ----------------------------------------------------------------------------
+# batching: one plan over several views == one plan per view
+# ----------------------------------------------------------------------------
+
+def test_batched_views_equal_single(R, orc):
+    cam, frames, vpose = room_frames(9, 64, 48, n_kf=3)
+    ks = [gpu_kf(R, fr, learnable=True).with_grad_buffers() for fr in frames]
+    poses = [fr.pose for fr in frames]
+    views = [R.View(cam.as_tuple(), p, 0, 3) for p in poses]
+    batch = R.Plan(ks, views)
+    rgb, depth, sil = batch.render_fwd()
+    rng = np.random.default_rng(1)
+    g_rgb = rng.normal(size=(3, batch.P)); g_d = rng.normal(size=batch.P)
+    tw_b = np_(batch.render_bwd(T(g_rgb), T(g_d), None))
+    gb = [np_(k.g_color).copy() for k in ks]
+    for k in ks:
+        k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+    for v, view in enumerate(views):
+        single = R.Plan(ks, [view])
+        r1, d1, s1 = single.render_fwd()
+        o = batch.offsets[v]
+        sl = slice(o, o + single.P)
+        assert np.array_equal(np_(r1), np_(rgb)[:, sl])
+        assert np.array_equal(np_(d1), np_(depth)[sl])
+        assert np.array_equal(np_(s1), np_(sil)[sl])
+        tw1 = np_(single.render_bwd(T(g_rgb[:, sl]), T(g_d[sl]), None))
+        assert np.array_equal(tw1[0], tw_b[v])
+    for k, g in zip(ks, gb):
+        assert np.allclose(np_(k.g_color), g, rtol=1e-5, atol=1e-7)
+
+
+def test_uneven_resolutions_batch(R, orc):
+    """Views of different sizes in one plan, each vs the oracle."""
+    cam, frames, vpose = room_frames(9, 64, 48, n_kf=3)
+    ks = [gpu_kf(R, fr) for fr in frames]
+    from paper_2506_02741_amd import synth
+    sizes = [(64, 48), (37, 23), (100, 75)]
+    views, oviews = [], []
+    for (w, h), fr in zip(sizes, frames):
+        c = synth.Camera(w * 525 / 640, w * 525 / 640, w / 2, h / 2, w, h)
+        views.append(R.View(c.as_tuple(), fr.pose, 0, 3))
+        oviews.append(orc.ViewSpec(c.as_tuple(), fr.pose, 0, 3))
+    plan = R.Plan(ks, views)
+    rgb, depth, sil = plan.render_fwd()
+    okfs = [oracle_kf(orc, f) for f in frames]
+    for v, ov in enumerate(oviews):
+        ref = orc.render(ov, okfs, margin=MARGIN)
+        o = plan.offsets[v]
+        sl = slice(o, o + ov.P)
+        check_images(rgb[:, sl], depth[sl], sil[sl], ref)
+
+
+# ----------------------------------------------------------------------------
+# determinism, capacity, edge cases
+# ----------------------------------------------------------------------------
+
+def test_deterministic(R):
+    cam, frames, vpose = room_frames(5, 80, 60)
+    k = gpu_kf(R, frames[0], learnable=True).with_grad_buffers()
+    plan = R.Plan([k], [R.View(cam.as_tuple(), vpose)])
+    rng = np.random.default_rng(2)
+    g = T(rng.normal(size=(3, plan.P)))
+    out = []
+    for _ in range(2):
+        k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+        imgs = [np_(x) for x in plan.render_fwd()]
+        tw = np_(plan.render_bwd(g, None, None))
+        out.append((imgs, tw, np_(k.g_color), np_(k.g_radius)))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    for i in (1, 2, 3):
+        assert np.array_equal(out[0][i], out[1][i])
+
+
+def test_capacity_overflow_is_reported_and_recoverable(R, orc):
+    from paper_2506_02741_amd import _lib
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr)
+    view = R.View(cam.as_tuple(), vpose)
+    keys, vals, ranges = orc.tile_lists(orc.ViewSpec(cam.as_tuple(), vpose), [oracle_kf(orc, fr)])
+    small = R.Plan([k], [view], pair_capacity=len(vals) // 3)
+    small.render_fwd()
+    rc, need = small.status(clear=True)
+    assert rc == _lib.VTGS_E_CAPACITY and need == len(vals)
+    plan, imgs = R.plan_checked([k], [view], pair_capacity=100, run=lambda p: p.render_fwd())
+    ref = orc.render(orc.ViewSpec(cam.as_tuple(), vpose), [oracle_kf(orc, fr)], margin=MARGIN)
+    check_images(*imgs, ref)
+
+
+def test_edge_cases(R, orc):
+    import torch
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr)
+    empty = R.Keyframe(cam.as_tuple(), fr.pose, np.zeros(0, np.int32), np.zeros(0), np.zeros((3, 0)),
+                       np.zeros(0), np.zeros(0))
+    # empty keyframe in the slice changes nothing
+    a = R.Plan([empty, k], [R.View(cam.as_tuple(), vpose, 0, 2)]).render_fwd()
+    b = R.Plan([k], [R.View(cam.as_tuple(), vpose)]).render_fwd()
+    for x, y in zip(a, b):
+        assert np.array_equal(np_(x), np_(y))
+    # camera turned around: everything culled -> background, silhouette 0
+    back = fr.pose.copy()
+    back[:, :3] = -back[:, :3]
+    back[:, 3] = -back[:, 3]
+    rgb, depth, sil = R.Plan([k], [R.View(cam.as_tuple(), back)], R.params(bg=(0.1, 0.2, 0.3))).render_fwd()
+    assert float(sil.abs().max()) == 0.0 and float(depth.abs().max()) == 0.0
+    assert np.allclose(np_(rgb)[:, 0], [0.1, 0.2, 0.3])
+    # 1x1 and ragged views vs the oracle
+    okf = oracle_kf(orc, fr)
+    for (w, h) in ((1, 1), (17, 9), (33, 47)):
+        c = (cam.fx, cam.fy, w / 2.0, h / 2.0, w, h)
+        imgs = R.Plan([k], [R.View(c, vpose)]).render_fwd()
+        ref = orc.render(orc.ViewSpec(c, vpose), [okf], margin=MARGIN)
+        check_images(*imgs, ref, max_marginal=1.0)
+
+
+# ----------------------------------------------------------------------------
+# autograd wrapper
+# ----------------------------------------------------------------------------
+
+def test_autograd_matches_oracle_and_fd(R, orc):
+    import torch
+    cam, frames, vpose = room_frames(11, 24, 18)
+    fr = frames[0]
+    # smooth setting: no alpha_min skip, a wide cut-off and opacity 0.3 so
+    # transmittance stays far above t_min (no stop decisions)
+    prm = dict(alpha_min=0.0, q_cut=60.0)
+    k = gpu_kf(R, fr, learnable=True)
+    k.opacity.fill_(0.3)
+    plan = R.Plan([k], [R.View(cam.as_tuple(), vpose)], R.params(**prm))
+    rng = np.random.default_rng(4)
+    w_rgb = T(rng.normal(size=(3, plan.P))); w_d = T(rng.normal(size=plan.P))
+    tw = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    k.color.requires_grad_(True); k.opacity.requires_grad_(True); k.radius.requires_grad_(True)
+    rgb, depth, sil = R.render(plan, tw)
+    loss = (rgb * w_rgb).sum() + (depth * w_d).sum()
+    loss.backward()
+    okf = oracle_kf(orc, fr)
+    okf.opacity[:] = 0.3
+    gref = orc.render_bwd(orc.ViewSpec(cam.as_tuple(), vpose), [okf], np_(w_rgb).astype(np.float64),
+                          np_(w_d).astype(np.float64), None, orc.params(**prm))
+    for got, name in ((k.color.grad, "color"), (k.opacity.grad, "opacity"), (k.radius.grad, "radius")):
+        ok, worst = grad_close(np_(got), gref[name])
+        assert ok, (name, worst)
+    ok, worst = grad_close(np_(tw.grad)[0], gref["twist"])
+    assert ok, worst
+    # FP32 central differences on a few opacities (smooth: thresholds off)
+    with torch.no_grad():
+        for i in rng.choice(k.n, 4, replace=False):
+            eps = 1e-2
+            vals = []
+            for s in (1, -1):
+                k.opacity[i] += s * eps
+                r2, d2, _ = plan.render_fwd()
+                vals.append(float((r2 * w_rgb).sum() + (d2 * w_d).sum()))
+                k.opacity[i] -= s * eps
+            fd = (vals[0] - vals[1]) / (2 * eps)
+            assert abs(fd - float(k.opacity.grad[i])) <= 2e-2 * max(1.0, abs(fd)), (fd, float(k.opacity.grad[i]))

@@ -1,0 +1,177 @@
+"""track_step and map_step through the C ABI against the oracle, one
+iteration from identical state, plus the behavioural tracking check.
+
+A first Adam step is -lr * m_hat / (sqrt(v_hat) + eps) = -lr g / (|g| + eps),
+i.e. about -lr sign(g): updates are compared where |g| is clearly above eps
+and the sign is therefore decided identically."""
+import math
+
+import numpy as np
+import pytest
+
+from scenes import oracle_kf, room_frames
+
+pytestmark = pytest.mark.gpu
+MARGIN = 2e-6
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    from paper_2506_02741_amd import render
+    return render
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def pose_error(T, Tref):
+    T = np.asarray(T, np.float64).reshape(3, 4); Tref = np.asarray(Tref, np.float64).reshape(3, 4)
+    Rc = T[:, :3].T; c = -Rc @ T[:, 3]
+    Rr = Tref[:, :3].T; cr = -Rr @ Tref[:, 3]
+    dR = Rc.T @ Rr
+    ang = math.degrees(math.acos(max(-1.0, min(1.0, (np.trace(dR) - 1) / 2))))
+    return float(np.linalg.norm(c - cr)), ang
+
+
+def test_track_one_iteration(R, orc):
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1, 160, 120)
+    kf = w["keyframe"]
+    cam = kf.cam.as_tuple()
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, cam, kf.pose)
+    view = R.View(cam, w["init_pose"], obs_rgb=kf.rgb, obs_depth=kf.depth).with_pose_adam()
+    plan = R.Plan([k], [view])
+    cfg = R.track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002)
+    loss = plan.track_step(cfg, iters=1)
+    assert plan.status()[0] == 0
+    L_ref, pose_ref, st, g_ref, _ = orc.track_iteration(
+        orc.ViewSpec(cam, w["init_pose"]), [oracle_kf(orc, kf)], kf.rgb, kf.depth,
+        dict(m=np.zeros(6), v=np.zeros(6), t=0))
+    assert abs(float(np_(loss)[0, 0]) - L_ref) <= 1e-4 * abs(L_ref)
+    assert np.all(np.abs(g_ref) > 1e-3 * np.abs(g_ref).max())
+    assert np.allclose(np_(view.pose).reshape(3, 4), pose_ref, atol=2e-6), (np_(view.pose), pose_ref)
+    ad = np_(view.pose_adam)
+    assert ad[12] == 1.0
+    assert np.allclose(ad[:6], 0.1 * g_ref, rtol=2e-3, atol=1e-6 * np.abs(g_ref).max())
+
+
+def test_map_then_track_converges(R, orc):
+    """Behavioural (the exact trajectory is not pinned): map the keyframe's
+    Gaussians against its own RGBD (Eq. 2), then track a new frame observed
+    at the keyframe pose from a 1 cm / 0.5 degree perturbation (Eq. 1).  The
+    mapping loss falls, and 40 tracking iterations reduce the loss and the
+    pose error.  Raw ingested Gaussians (o = 0.99, one-pixel footprint) blur
+    slanted surfaces in depth order, which moves the tracking optimum; the
+    paper tracks against mapped Gaussians."""
+    import torch
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1, 320, 240)
+    kf = w["keyframe"]
+    cam = kf.cam.as_tuple()
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, cam, kf.pose, learnable=True).with_adam()
+    mp = R.Plan([k], [R.View(cam, kf.pose, obs_rgb=kf.rgb, obs_depth=kf.depth)])
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ml = [float(mp.map_step(step)[0]) for _ in range(150)]
+    assert mp.status()[0] == 0
+    assert np.mean(ml[-10:]) < 0.7 * np.mean(ml[:3]), (ml[:3], ml[-10:])
+    view = R.View(cam, w["init_pose"], obs_rgb=kf.rgb, obs_depth=kf.depth).with_pose_adam()
+    plan = R.Plan([k], [view])
+    e0 = pose_error(w["init_pose"], w["true_pose"])
+    loss = np_(plan.track_step(R.track_cfg(), iters=40))[:, 0]
+    assert plan.status()[0] == 0
+    e1 = pose_error(np_(view.pose), w["true_pose"])
+    assert loss[-5:].mean() < loss[:3].mean(), loss
+    assert e1[0] < e0[0] and e1[1] < e0[1], (e0, e1)
+
+
+def test_track_batched_views_match_single(R):
+    """Two tracking requests in one plan follow the same trajectory as each
+    alone (the pose path has no atomics, so bit-identical)."""
+    from paper_2506_02741_amd import synth
+    ws = [synth.tracking_workload(s, 96, 72) for s in (1, 2)]
+    ks = [R.Keyframe.ingest(w["keyframe"].depth, w["keyframe"].rgb, w["keyframe"].cam.as_tuple(),
+                            w["keyframe"].pose) for w in ws]
+
+    def views():
+        return [R.View(w["keyframe"].cam.as_tuple(), w["init_pose"], i, 1, w["keyframe"].rgb,
+                       w["keyframe"].depth).with_pose_adam() for i, w in enumerate(ws)]
+    vb = views()
+    R.Plan(ks, vb).track_step(R.track_cfg(), iters=5)
+    for i in range(2):
+        vs = views()[i]
+        R.Plan(ks, [vs]).track_step(R.track_cfg(), iters=5)
+        assert np.array_equal(np_(vs.pose), np_(vb[i].pose))
+
+
+def _oracle_map_iteration(orc, cams, poses, okfs, obs, cfg):
+    """Eq. 2 per view, gradients summed over views, one Adam step."""
+    N = sum(k.n for k in okfs)
+    gc = np.zeros((3, N)); go = np.zeros(N); gr = np.zeros(N)
+    losses = []
+    for cam, pose, (orgb, odep) in zip(cams, poses, obs):
+        v = orc.ViewSpec(cam, pose, 0, len(okfs))
+        out = orc.render(v, okfs, margin=MARGIN)
+        L, g_rgb, g_d = orc.map_loss(cam[5], cam[4], out["rgb"], out["depth"], orgb, odep,
+                                     cfg["rho"], cfg["tau"], cfg["sigma"])
+        losses.append(L)
+        g = orc.render_bwd(v, okfs, g_rgb, g_d, None)
+        gc += g["color"]; go += g["opacity"]; gr += g["radius"]
+    return np.array(losses), gc, go, gr
+
+
+def _section_inputs(frames, seed=0):
+    """Gaussians at every pixel of each frame (all depths are valid in the
+    generated rooms) with seeded colour, opacity and radius: the same arrays
+    go to the oracle and to the GPU."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in frames:
+        n = f.depth.size
+        out.append(dict(pix=np.arange(n, dtype=np.uint32), depth=f.depth.ravel().copy(),
+                        color=np.clip(f.rgb.reshape(3, -1) + rng.uniform(-0.1, 0.1, (3, n)), 0, 1).astype(np.float32),
+                        opacity=rng.uniform(0.6, 0.95, n).astype(np.float32),
+                        radius=rng.uniform(0.002, 0.012, n).astype(np.float32)))
+    return out
+
+
+def test_map_one_iteration(R, orc):
+    import torch
+    cam, frames, _ = room_frames(9, 64, 48, n_kf=2)
+    assert all(np.all(f.depth > 0) for f in frames)
+    inp = _section_inputs(frames)
+    ks = [R.Keyframe(cam.as_tuple(), f.pose, d["pix"].astype(np.int32), d["depth"], d["color"], d["opacity"],
+                     d["radius"], learnable=True).with_adam() for f, d in zip(frames, inp)]
+    okfs = [orc.Keyframe(cam.as_tuple(), f.pose, d["pix"], d["depth"], d["color"], d["opacity"], d["radius"])
+            for f, d in zip(frames, inp)]
+    views = [R.View(cam.as_tuple(), f.pose, 0, 2, f.rgb, f.depth) for f in frames]
+    plan = R.Plan(ks, views)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cfg = dict(rho=0.8, tau=0.2, sigma=1.0)
+    loss = np_(plan.map_step(step, R.map_cfg(**cfg)))
+    assert plan.status()[0] == 0 and int(step.item()) == 1
+    L_ref, gc, go, gr = _oracle_map_iteration(orc, [cam.as_tuple()] * 2, [f.pose for f in frames], okfs,
+                                              [(f.rgb, f.depth) for f in frames], cfg)
+    assert np.allclose(loss, L_ref, rtol=1e-4), (loss, L_ref)
+    n0 = ks[0].n
+    lrs = dict(color=0.0025, opacity=0.05, radius=0.005)
+    for i, (k, d) in enumerate(zip(ks, inp)):
+        sl = slice(0, n0) if i == 0 else slice(n0, n0 + k.n)
+        c0, o0, r0 = d["color"].astype(np.float64), d["opacity"].astype(np.float64), d["radius"].astype(np.float64)
+        g_logit = go[sl] * o0 * (1 - o0)
+        g_log = gr[sl] * r0
+        new_c, new_o, new_r = (np_(k.color).astype(np.float64), np_(k.opacity).astype(np.float64),
+                               np_(k.radius).astype(np.float64))
+        for got, old, g, lr, name in (
+                (new_c, c0, gc[:, sl], lrs["color"], "color"),
+                (np.log(new_o / (1 - new_o)), np.log(o0 / (1 - o0)), g_logit, lrs["opacity"], "opacity"),
+                (np.log(new_r), np.log(r0), g_log, lrs["radius"], "radius")):
+            step_ref = -lr * g / (np.abs(g) + 1e-8)
+            sure = np.abs(g) > 1e-6
+            assert sure.mean() > 0.5, name
+            d_ = (got - old)[sure]
+            assert np.all(np.abs(d_ - step_ref[sure]) <= 2e-3 * lr + 2e-6), name
+            assert np.all(np.abs(got - old) <= lr * 1.001 + 2e-6), name

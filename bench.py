@@ -161,6 +161,68 @@ def batched_vs_single(iters):
                 speedup=ts / tb)
 
 
+def serving_run(seconds, rate, n_sections, budget_gib, seed=4):
+    """Poisson render/track requests against a device-resident map of
+    n_sections x 10 keyframes at 1200x680, stride 2.  The map is built from
+    3 ray-cast sections replicated on the device up to n_sections (a stand-in
+    that keeps generation short; every section is its own copy in HBM)."""
+    import numpy as np
+    import torch
+    from paper_2506_02741_amd import render as R
+    from paper_2506_02741_amd import serve
+    from paper_2506_02741_amd import synth
+    t0 = time.perf_counter()
+    m = synth.serving_sections(seed)
+    base = []
+    for sec in m["sections"]:
+        base.append([R.Keyframe.ingest(f.depth, f.rgb, f.cam.as_tuple(), f.pose, stride=2)
+                     for f in sec])
+    kfs, sections = [], []
+    for s in range(n_sections):
+        src = base[s % len(base)]
+        sections.append((len(kfs), len(src)))
+        for k in src:
+            kfs.append(R.Keyframe(k.cam, k.pose, k.pix, k.depth, k.color.clone(), k.opacity.clone(),
+                                  k.radius.clone()))
+    n_gauss = sum(k.n for k in kfs)
+    # observations for track requests: a few frames per resolution per unique section
+    rng = np.random.default_rng(seed)
+    cams = [synth.camera_for(*wh).as_tuple() for wh in synth.RESOLUTIONS]
+    obs = {}
+    for u, sec in enumerate(m["sections"]):
+        for ci, c in enumerate(cams):
+            fr = sec[int(rng.integers(0, len(sec)))]
+            cam = synth.Camera(*c)
+            o = synth.frame(m["scene"], cam, fr.pose)
+            obs[(u, ci)] = (o.pose, torch.tensor(o.rgb, device="cuda"),
+                            torch.tensor(o.depth, device="cuda"))
+    gen_s = time.perf_counter() - t0
+
+    def poses_for(rng, sec, cam):
+        ci = cams.index(cam)
+        true = obs[(sec % len(base), ci)][0]
+        return synth.perturb_pose(true, rng, 0.01, 0.5).astype(np.float32), (sec % len(base), ci)
+
+    def obs_for(sec, cam, key):
+        _, rgb, depth = obs[key]
+        return rgb, depth
+    trace = serve.poisson_trace(np.random.default_rng(seed + 1), rate, seconds, n_sections, cams,
+                                poses_for, obs_for)
+    srv = serve.Server(kfs, sections, budget_bytes=int(budget_gib * (1 << 30)), max_active=64)
+    # warm the kernels and the allocator on a short prefix
+    warm = serve.Server(kfs, sections, budget_bytes=int(budget_gib * (1 << 30)), max_active=64)
+    warm.run_trace(serve.poisson_trace(np.random.default_rng(seed + 2), rate, 0.3, n_sections, cams,
+                                       poses_for, obs_for), realtime=False)
+    rep = srv.run_trace(trace, realtime=True)
+    rep.update(offered_req_per_s=rate, map_gaussians=n_gauss, sections=n_sections,
+               keyframes=len(kfs), budget_gib=budget_gib, peak_admitted_gib=srv.peak_mem / (1 << 30),
+               generation_s=gen_s,
+               workload="Poisson %g req/s for %g s, 60%% render / 40%% 20-iteration track, "
+                        "resolutions 320x240/640x480/1200x680, map of %d sections x 10 keyframes "
+                        "1200x680 stride 2" % (rate, seconds, n_sections))
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +232,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-sections", type=int, default=30)
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path has no multi-GPU "
@@ -185,27 +252,35 @@ def main():
     w, k, view, plan, init = tracking_setup()
     cfg = R.track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002)
     loss = torch.zeros(40, 1, device="cuda")
-    log("bench: warmup %d iterations" % args.warmup)
-    run_frames(plan, view, init, cfg, args.warmup, loss)
+    # a non-default stream: each 40-iteration frame is one replay of a
+    # captured graph of the iteration's kernels
+    stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    rc, need = plan.status()
+    log("bench: warmup %d iterations" % args.warmup)
+    with torch.cuda.stream(stream):
+        run_frames(plan, view, init, cfg, args.warmup, loss)
+    torch.cuda.synchronize()
+    rc, need = plan.status(stream=stream)
     if rc != 0:
         raise SystemExit("plan status %d (pairs needed %d)" % (rc, need))
 
     log("bench: timing %d iterations" % args.steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run_frames(plan, view, init, cfg, args.steps, loss)
+    with torch.cuda.stream(stream):
+        run_frames(plan, view, init, cfg, args.steps, loss)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    rc, need = plan.status()
+    rc, need = plan.status(stream=stream)
     assert rc == 0, rc
     value = 640 * 480 * args.steps / dt / 1e6
 
-    # per-stage durations from HIP events on the launch stream
+    # per-stage durations from HIP events on the launch stream (eager
+    # launches while timing is on)
     log("bench: stage timing")
     plan.timing(True)
-    run_frames(plan, view, init, cfg, 80, loss)
+    with torch.cuda.stream(stream):
+        run_frames(plan, view, init, cfg, 80, loss)
     stages = plan.timing(False)
     avg = {s: ms / n for s, (ms, n) in stages.items()}
     dom = max(stages, key=lambda s: stages[s][0])
@@ -237,6 +312,12 @@ def main():
         log("bench: batched vs one view per launch")
         batched = batched_vs_single(args.batched_iters)
 
+    serving = None
+    if not args.no_serving:
+        log("bench: serving %g s at %g req/s" % (args.serve_seconds, args.serve_rate))
+        serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_sections,
+                              args.serve_budget_gib)
+
     out = dict(metric="fwd+bwd Mpix/s at 640x480", value=value, unit="Mpix/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
@@ -244,7 +325,7 @@ def main():
                config=dict(workload="tracking 640x480: 1 keyframe, 307,200 view-tied Gaussians, "
                                     "40-iteration frames of fwd + Eq.1 + bwd to twist + pose step",
                            global_batch=1, seq_len=0, parallelism="none"),
-               roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched)
+               roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched, serving=serving)
     print(json.dumps(out), flush=True)
 
 

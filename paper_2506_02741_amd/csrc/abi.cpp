@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +20,40 @@ using namespace vtgs;
 namespace {
 
 thread_local std::string g_err;
+
+// Pinned host staging buffers for descriptor uploads, reused across plans
+// (a request loop creates plans often; pinned allocation is slow).  A buffer
+// returns to the pool only after the upload that read it has completed.
+std::mutex g_pin_mu;
+std::vector<std::pair<size_t, void *>> g_pin_free;  // (capacity, pointer)
+
+void *pinned_take(size_t bytes, size_t *cap) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (size_t i = 0; i < g_pin_free.size(); i++)
+      if (g_pin_free[i].first >= bytes) {
+        void *p = g_pin_free[i].second;
+        *cap = g_pin_free[i].first;
+        g_pin_free.erase(g_pin_free.begin() + i);
+        return p;
+      }
+  }
+  size_t b = 4096;
+  while (b < bytes) b <<= 1;
+  void *p = nullptr;
+  if (hipHostMalloc(&p, b) != hipSuccess) return nullptr;
+  *cap = b;
+  return p;
+}
+
+void pinned_give(void *p, size_t cap) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (g_pin_free.size() < 64) {
+    g_pin_free.push_back({cap, p});
+    return;
+  }
+  (void)hipHostFree(p);
+}
 
 int fail(int code, const std::string &msg) {
   g_err = msg;
@@ -60,10 +96,16 @@ struct vtgs_plan {
   char *ws = nullptr;
   Ws w{};
   void *pinned = nullptr;
+  size_t pinned_cap = 0;
   hipEvent_t upload_done = nullptr;
   bool bound = false, fwd_done = false;
   // stage timing (HIP events around every stage while enabled)
   bool timing = false;
+  // captured tracking iterations (replayed by track_step)
+  hipGraphExec_t graph = nullptr;
+  int32_t graph_iters = 0;
+  float *graph_loss = nullptr;
+  vtgs_track_cfg graph_cfg{};
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_used;  // stage, (start, stop)
 };
@@ -132,6 +174,7 @@ void make_ws(vtgs_plan *p) {
   char *b = p->ws;
   w.flags = reinterpret_cast<uint32_t *>(b + p->r_hdr.off);
   w.n_pairs = reinterpret_cast<unsigned long long *>(b + p->r_hdr.off + 8);
+  w.iter = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 16);
   char *d = b + p->r_desc.off;
   w.kfs = reinterpret_cast<const DevKF *>(d + p->desc_kf);
   w.views = reinterpret_cast<const DevView *>(d + p->desc_view);
@@ -234,6 +277,18 @@ int run_forward(vtgs_plan *p, float *rgb, float *depth, float *sil, hipStream_t 
   STAGE(p, ST_SORT, st, launch_sort_tiles(w, st));
   STAGE(p, ST_FWD, st, launch_composite_fwd(w, rgb, depth, sil, st));
   p->fwd_done = true;
+  return VTGS_OK;
+}
+
+// One tracking iteration of every view: forward into the internal images,
+// Eq. 1 loss and gradients, backward to the twist, Adam step + retraction.
+int track_iteration(vtgs_plan *p, const vtgs_track_cfg &cfg, float *loss, hipStream_t st) {
+  const Ws &w = p->w;
+  const int64_t P = p->P;
+  if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
+  STAGE(p, ST_LOSS, st, launch_track_loss(w, cfg, st));
+  STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 1, st));
+  STAGE(p, ST_UPDATE, st, launch_track_update(w, cfg, loss, st));
   return VTGS_OK;
 }
 
@@ -425,8 +480,9 @@ void vtgs_plan_destroy(vtgs_plan *p) {
     (void)hipEventSynchronize(p->upload_done);
     (void)hipEventDestroy(p->upload_done);
   }
-  if (p->pinned) (void)hipHostFree(p->pinned);
+  if (p->pinned) pinned_give(p->pinned, p->pinned_cap);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->graph) (void)hipGraphExecDestroy(p->graph);
   delete p;
 }
 
@@ -451,7 +507,10 @@ int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
                                         " bytes, needs " + std::to_string(p->ws_bytes));
     hipStream_t st = (hipStream_t)stream;
     if (p->upload_done) HIP_OK(hipEventSynchronize(p->upload_done));
-    if (!p->pinned) HIP_OK(hipHostMalloc(&p->pinned, std::max<int64_t>(p->desc_bytes, 256)));
+    if (!p->pinned) {
+      p->pinned = pinned_take((size_t)std::max<int64_t>(p->desc_bytes, 256), &p->pinned_cap);
+      if (!p->pinned) return fail(VTGS_E_HIP, "plan_bind: pinned host allocation failed");
+    }
     if (!p->upload_done) HIP_OK(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming));
     char *h = (char *)p->pinned;
     std::memset(h, 0, p->desc_bytes);
@@ -462,6 +521,10 @@ int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
     if (!p->kf_use.empty()) std::memcpy(h + p->desc_use, p->kf_use.data(), p->kf_use.size() * sizeof(DevKFUse));
     p->ws = (char *)ws;
     make_ws(p);
+    if (p->graph) {  // captured pointers refer to the previous binding
+      (void)hipGraphExecDestroy(p->graph);
+      p->graph = nullptr;
+    }
     HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(p->upload_done, st));
     HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
@@ -539,15 +602,46 @@ int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, floa
                                     " needs obs_rgb, obs_depth and pose_adam");
     }
     hipStream_t st = (hipStream_t)stream;
-    const Ws &w = p->w;
-    const int64_t P = p->P;
-    for (int it = 0; it < iters; it++) {
-      if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
-      STAGE(p, ST_LOSS, st, launch_track_loss(w, *cfg, st));
-      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 1, st));
-      STAGE(p, ST_UPDATE, st,
-            launch_track_update(w, *cfg, loss ? loss + (int64_t)it * p->views.size() : nullptr, st));
+    HIP_OK(launch_fill_u32(p->w.iter, 0xFFFFFFFFu, 1, st));
+    if (iters == 0) return VTGS_OK;
+    // Replay a captured graph of `g` iterations when the stream can be
+    // captured (not the legacy default stream) and stage timing is off.
+    const bool graphs = st != nullptr && !p->timing && iters >= 2 && !std::getenv("VTGS_NO_GRAPH");
+    if (!graphs) {
+      for (int it = 0; it < iters; it++)
+        if (int rc = track_iteration(p, *cfg, loss, st)) return rc;
+      return VTGS_OK;
     }
+    const int32_t g = iters <= 64 ? iters : 1;
+    if (!p->graph || p->graph_iters != g || p->graph_loss != loss ||
+        std::memcmp(&p->graph_cfg, cfg, sizeof(vtgs_track_cfg)) != 0) {
+      if (p->graph) {
+        HIP_OK(hipGraphExecDestroy(p->graph));
+        p->graph = nullptr;
+      }
+      HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      int rc = VTGS_OK;
+      for (int it = 0; it < g && rc == VTGS_OK; it++) rc = track_iteration(p, *cfg, loss, st);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &graph);
+      if (rc != VTGS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return fail(VTGS_E_HIP, std::string("stream capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&p->graph, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        p->graph = nullptr;
+        return fail(VTGS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      }
+      p->graph_iters = g;
+      p->graph_loss = loss;
+      p->graph_cfg = *cfg;
+    }
+    for (int done = 0; done + g <= iters; done += g) HIP_OK(hipGraphLaunch(p->graph, st));
+    for (int it = (iters / g) * g; it < iters; it++)
+      if (int rc = track_iteration(p, *cfg, loss, st)) return rc;
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "track_step: unexpected exception");

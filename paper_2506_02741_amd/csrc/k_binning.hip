@@ -39,6 +39,9 @@ __global__ void k_fill_f32(float *p, float v, int64_t n) {
 // M = Tv * Tk^-1 = [Rv Rk^T | tv - (Rv Rk^T) tk], fixed summation order.
 __global__ void k_setup(Ws ws) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  // one more pass of the pipeline: the tracking update writes its loss at
+  // this index, so a captured iteration needs no per-iteration argument
+  if (s == 0) *ws.iter += 1u;
   if (s >= ws.n_segs) return;
   DevSeg &sg = ws.segs[s];
   const float *Tv = ws.views[sg.view].pose;
@@ -372,7 +375,8 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_setup(const Ws &ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(blocks_for(ws.n_segs, 64)), dim3(64), 0, st, ws);
+  hipLaunchKernelGGL(k_setup, dim3(blocks_for(ws.n_segs > 0 ? ws.n_segs : 1, 64)), dim3(64), 0, st,
+                     ws);
   return hipGetLastError();
 }
 

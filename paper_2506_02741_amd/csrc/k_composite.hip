@@ -84,10 +84,25 @@ __device__ __forceinline__ bool wave_skip(const float4 &e0, float R, float bx0, 
   return __builtin_amdgcn_readfirstlane((int)miss) != 0;
 }
 
+// Gather entry `id` of the view's records (an id out of range, which a
+// consistent list never holds, yields an entry that every wave skips).
+__device__ __forceinline__ void load_entry(const Ws &ws, const DevView &vw, uint32_t id,
+                                           float4 &e0, float4 &e1, float4 &e2) {
+  if (id < (uint32_t)vw.n_rec) {
+    const float4 *A = ws.recA + 3 * ((int64_t)vw.rec_base + id);
+    e0 = A[0]; e1 = A[1]; e2 = A[2];
+  } else {
+    e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
+    e1 = make_float4(0.f, 0.f, 1.f, 0.f);
+    e2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, float *out_depth,
                                                          float *out_sil) {
   constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
+  constexpr int PER = (BATCH + NT - 1) / NT;  // list entries each thread stages per batch
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
   const int t = blockIdx.x;
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
@@ -115,48 +130,64 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
   }
   const float amin = ws.amin, amax = ws.amax, tmin = ws.tmin, qcut = ws.qcut;
 
+  // next batch's entries, gathered from global memory into registers while
+  // the current batch is composited
+  float4 p0[PER], p1[PER], p2[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = threadIdx.x + k * NT;
+    if (i < BATCH && start + i < end) load_entry(ws, vw, ws.ids[start + i], p0[k], p1[k], p2[k]);
+  }
+
   for (int b = start; b < end; b += BATCH) {
     bool mine = true;
 #pragma unroll
     for (int k = 0; k < PPT; k++) mine &= done[k];
     if (__syncthreads_count(mine) == NT) break;
     const int nb = min(BATCH, end - b);
-    for (int i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t id = ws.ids[b + i];
-      if (id < (uint32_t)vw.n_rec) {
-        const float4 *A = ws.recA + 3 * ((int64_t)vw.rec_base + id);
-        e0s[i] = A[0]; e1s[i] = A[1]; e2s[i] = A[2];
-      } else {  // never happens for a consistent list; an empty entry is skipped
-        e0s[i] = make_float4(-1e30f, -1e30f, 0.f, 0.f);
-        e1s[i] = make_float4(0.f, 0.f, 1.f, 0.f);
-        e2s[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (i < nb) { e0s[i] = p0[k]; e1s[i] = p1[k]; e2s[i] = p2[k]; }
     }
     __syncthreads();
+    const int nx = b + BATCH;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (i < BATCH && nx + i < end) load_entry(ws, vw, ws.ids[nx + i], p0[k], p1[k], p2[k]);
+    }
     if (__builtin_amdgcn_readfirstlane((int)(ballot64(!mine) != 0ull)) == 0) continue;
+    float4 n0 = e0s[0], n1 = e1s[0], n2 = e2s[0];
     for (int j = 0; j < nb; j++) {
-      const float4 e0 = e0s[j];
-      const float4 e1 = e1s[j];
+      const float4 e0 = n0, e1 = n1, e2 = n2;
+      if (j + 1 < nb) { n0 = e0s[j + 1]; n1 = e1s[j + 1]; n2 = e2s[j + 1]; }
       if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
+      const uint32_t pos = (uint32_t)(b - start + j + 1);
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
-        if (done[k]) continue;
         float dx, dy;
         const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
-        if (!(q <= qcut)) continue;
         const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
         const float a = fminf(amax, e1.y * G);
-        if (!(a >= amin)) continue;
+        const bool ok = !done[k] && (q <= qcut) && (a >= amin);
         const float Tn = T[k] * (1.0f - a);
-        if (Tn < tmin) { done[k] = true; continue; }
-        const float4 e2 = e2s[j];
-        const float wgt = a * T[k];
+        const bool stop = ok && (Tn < tmin);
+        const bool take = ok && !stop;
+        done[k] = done[k] || stop;
+        const float wgt = take ? a * T[k] : 0.f;
         C0[k] = fmaf(e2.x, wgt, C0[k]);
         C1[k] = fmaf(e2.y, wgt, C1[k]);
         C2[k] = fmaf(e2.z, wgt, C2[k]);
         D[k] = fmaf(e1.z, wgt, D[k]);
-        T[k] = Tn;
-        last[k] = (uint32_t)(b - start + j + 1);
+        T[k] = take ? Tn : T[k];
+        last[k] = take ? pos : last[k];
+      }
+      if ((j & 31) == 31) {
+        bool all = true;
+#pragma unroll
+        for (int k = 0; k < PPT; k++) all &= done[k];
+        if (__builtin_amdgcn_readfirstlane((int)(ballot64(!all) != 0ull)) == 0) break;
       }
     }
   }
@@ -177,12 +208,45 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
   }
 }
 
+// Backward staging of one list entry: the forward record, the camera-frame
+// centre and learnable flag, and (slot mode) the entry's (record, tile) slot.
+struct BwdEntry {
+  float4 e0, e1, e2, eb;
+  uint32_t slot;
+};
+
+template <bool kSlots>
+__device__ __forceinline__ void load_bwd_entry(const Ws &ws, const DevView &vw, uint32_t id, int tx,
+                                               int ty, BwdEntry &E) {
+  if (id < (uint32_t)vw.n_rec) {
+    const int rec = vw.rec_base + (int)id;
+    const float4 *A = ws.recA + 3 * (int64_t)rec;
+    E.e0 = A[0]; E.e1 = A[1]; E.e2 = A[2];
+    E.eb = ws.recB[rec];
+    E.slot = 0xffffffffu;
+    if (kSlots) {
+      const uint2 rc = ws.rect[rec];
+      const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
+      const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
+      if (sl < (uint64_t)ws.cap) E.slot = sl;
+      else E.eb.z = 0.f;  // only after a capacity overflow
+    }
+  } else {
+    E.e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
+    E.e1 = make_float4(0.f, 0.f, 1.f, 0.f);
+    E.e2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    E.eb = make_float4(0.f, 0.f, 0.f, 0.f);
+    E.slot = 0xffffffffu;
+  }
+}
+
 template <int TILE, int BATCH, int MODE>
 __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_rgb,
                                                          const float *g_depth,
                                                          const float *g_sil) {
   constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
   constexpr int NW = NT / kWave;
+  constexpr int PER = (BATCH + NT - 1) / NT;
   constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
   constexpr int AB = kSlots ? BATCH : 1;
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
@@ -240,32 +304,31 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   const float amin = ws.amin, amax = ws.amax, qcut = ws.qcut;
   const float vfx = vw.fx, vfy = vw.fy;
 
+  // batches walk the list from the block's last contributor towards the front
+  BwdEntry st[PER];
+  {
+    const int lo = max(start, stop - BATCH);
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (i < BATCH && lo + i < stop) load_bwd_entry<kSlots>(ws, vw, ws.ids[lo + i], tx, ty, st[k]);
+    }
+  }
   for (int hi = stop; hi > start; hi -= BATCH) {
     const int lo = max(start, hi - BATCH);
     const int nb = hi - lo;
     __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += NT) {
-      const uint32_t id = ws.ids[lo + i];
-      const bool ok = id < (uint32_t)vw.n_rec;
-      const int rec = vw.rec_base + (ok ? (int)id : 0);
-      const float4 *A = ws.recA + 3 * (int64_t)rec;
-      float4 e0 = A[0], e1 = A[1], e2 = A[2];
-      float4 eb = ws.recB[rec];
-      if (!ok) {  // never happens for a consistent list; an empty entry is skipped
-        e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
-        e1 = make_float4(0.f, 0.f, 1.f, 0.f);
-        eb.z = 0.f;
-      }
-      e0s[i] = e0; e1s[i] = e1; e2s[i] = e2;
-      const float z = e1.z, iz = 1.0f / z;
-      ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * eb.x * iz * iz, -vfy * eb.y * iz * iz);
-      eps_[i] = make_float4(eb.x, eb.y, 2.0f * e2.w * e2.w * iz, eb.z);
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (i >= nb) continue;
+      const BwdEntry &E = st[k];
+      e0s[i] = E.e0; e1s[i] = E.e1; e2s[i] = E.e2;
+      const float iz = 1.0f / E.e1.z;
+      ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * E.eb.x * iz * iz, -vfy * E.eb.y * iz * iz);
+      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, E.eb.z);
       if (kSlots) {
-        const uint2 rc = ws.rect[rec];
-        const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
-        const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
-        slot_s[i] = sl;
-        if (!(sl < (uint64_t)ws.cap)) eps_[i].w = 0.f;  // only after a capacity overflow
+        slot_s[i] = E.slot;
 #pragma unroll
         for (int ww = 0; ww < NW; ww++)
 #pragma unroll
@@ -273,44 +336,57 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       }
     }
     __syncthreads();
+    {
+      const int nlo = max(start, lo - BATCH);
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int i = threadIdx.x + k * NT;
+        if (i < BATCH && nlo + i < lo) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
+      }
+    }
+    float4 n0 = e0s[nb - 1], n1 = e1s[nb - 1], n2 = e2s[nb - 1], nj = ejs[nb - 1], np = eps_[nb - 1];
     for (int j = nb - 1; j >= 0; j--) {
-      const float4 e0 = e0s[j];
-      const float4 e1 = e1s[j];
+      const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
+      if (j > 0) {
+        n0 = e0s[j - 1]; n1 = e1s[j - 1]; n2 = e2s[j - 1]; nj = ejs[j - 1]; np = eps_[j - 1];
+      }
       if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
       const int idx = lo + j - start;
-      const float4 e2 = e2s[j];
-      const float4 ej = ejs[j];
-      const float4 ep = eps_[j];
-      float sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, so = 0.f, sr = 0.f;
+      bool ok[PPT];
+      float dxs[PPT], dys[PPT], Gs[PPT], as[PPT];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
-        if (idx >= (int)last[k]) continue;
-        float dx, dy;
-        const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
-        if (!(q <= qcut)) continue;
-        const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-        const float oG = e1.y * G;
-        const float a = fminf(amax, oG);
-        if (!(a >= amin)) continue;
-        any = true;
+        const float q = quad(e0, e1.x, px[k], py[k], dxs[k], dys[k]);
+        Gs[k] = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+        as[k] = fminf(amax, e1.y * Gs[k]);
+        ok[k] = (idx < (int)last[k]) && (q <= qcut) && (as[k] >= amin);
+        any = any || ok[k];
+      }
+      if (__builtin_amdgcn_readfirstlane((int)(ballot64(any) != 0ull)) == 0) continue;
+      float sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, so = 0.f, sr = 0.f;
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        const float a = as[k], G = Gs[k], oG = e1.y * G;
         const float om = 1.0f - a;
-        T[k] = T[k] * __builtin_amdgcn_rcpf(om);
-        const float wgt = a * T[k];
+        const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
+        T[k] = Tk;
+        const float wgt = ok[k] ? a * Tk : 0.f;
         float dLda = gC0[k] * (e2.x - BC0[k]);
         dLda = fmaf(gC1[k], e2.y - BC1[k], dLda);
         dLda = fmaf(gC2[k], e2.z - BC2[k], dLda);
         dLda = fmaf(gD[k], e1.z - BD[k], dLda);
         dLda = fmaf(gS[k], 1.0f - BS[k], dLda);
-        dLda *= T[k];
-        BC0[k] = fmaf(a, e2.x, om * BC0[k]);
-        BC1[k] = fmaf(a, e2.y, om * BC1[k]);
-        BC2[k] = fmaf(a, e2.z, om * BC2[k]);
-        BD[k] = fmaf(a, e1.z, om * BD[k]);
-        BS[k] = fmaf(a, 1.0f, om * BS[k]);
+        dLda = ok[k] ? dLda * Tk : 0.f;
+        BC0[k] = ok[k] ? fmaf(a, e2.x, om * BC0[k]) : BC0[k];
+        BC1[k] = ok[k] ? fmaf(a, e2.y, om * BC1[k]) : BC1[k];
+        BC2[k] = ok[k] ? fmaf(a, e2.z, om * BC2[k]) : BC2[k];
+        BD[k] = ok[k] ? fmaf(a, e1.z, om * BD[k]) : BD[k];
+        BS[k] = ok[k] ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
         const bool pass = oG <= amax;
         const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
         // t = J^T Q d
+        const float dx = dxs[k], dy = dys[k];
         const float qb = e0.w;
         const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
         const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
@@ -335,7 +411,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           sr = fmaf(dLdq, -2.0f * e2.w * tt, sr);
         }
       }
-      if (kSlots && ep.w != 0.f && ballot64(any) != 0ull) {
+      if (kSlots && ep.w != 0.f) {
         const float r0 = wave_sum(sc0), r1 = wave_sum(sc1), r2 = wave_sum(sc2);
         const float r3 = wave_sum(so), r4 = wave_sum(sr);
         if (lane_id() == 0) {
@@ -362,14 +438,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   if (kSlots) {
     // list entries past every pixel's last contributor: zero slots
     for (int i = stop + (int)threadIdx.x; i < end; i += NT) {
-      const uint32_t id = ws.ids[i];
-      if (!(id < (uint32_t)vw.n_rec)) continue;
-      const int rec = vw.rec_base + (int)id;
-      const uint2 rc = ws.rect[rec];
-      const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
-      const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
-      if (!(sl < (uint64_t)ws.cap)) continue;
-      float *o = ws.slots + 5 * (int64_t)sl;
+      BwdEntry E;
+      load_bwd_entry<true>(ws, vw, ws.ids[i], tx, ty, E);
+      if (E.slot == 0xffffffffu) continue;
+      float *o = ws.slots + 5 * (int64_t)E.slot;
 #pragma unroll
       for (int c = 0; c < 5; c++) o[c] = 0.f;
     }

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kNT) void k_track_update(Ws ws, vtgs_track_cfg cfg,
   reduce_view(ws, v, g, &L, lds);
   if (threadIdx.x != 0) return;
   const DevView &vw = ws.views[v];
-  if (loss) loss[v] = L;
+  if (loss) loss[(int64_t)(*ws.iter) * ws.n_views + v] = L;
   bool finite = __builtin_isfinite(L);
   for (int c = 0; c < 6; c++) finite &= __builtin_isfinite(g[c]);
   if (!finite) { atomicOr(ws.flags, kFlagNonfinite); return; }

@@ -64,6 +64,7 @@ struct Ws {
   // header
   uint32_t *flags;
   unsigned long long *n_pairs;
+  uint32_t *iter;              // tracking iteration counter (bumped by setup)
   // descriptors
   const DevKF *kfs;
   const DevView *views;

@@ -380,3 +380,32 @@ def uneven_workload(seed=3, n_sections=3, kf_per_section=8, n_views=16):
         sections.append([frame(scene, camera_for(*wh), T) for wh, T in zip(res, poses)])
     views = [int(x) for x in rng.integers(0, n_sections * kf_per_section, size=n_views)]
     return dict(scene=scene, sections=sections, views=views)
+
+
+def strided_frame(scene, cam: Camera, pose, stride):
+    """A full-resolution frame whose depth/RGB are ray-cast only at the
+    stride grid (the only pixels a stride-s keyframe ties Gaussians to);
+    other pixels hold depth 0."""
+    sub = Camera(cam.fx / stride, cam.fy / stride, cam.cx / stride, cam.cy / stride,
+                 (cam.width + stride - 1) // stride, (cam.height + stride - 1) // stride)
+    d, rgb, _ = ray_cast(scene, sub, pose)
+    depth = np.zeros((cam.height, cam.width), np.float32)
+    col = np.zeros((3, cam.height, cam.width), np.float32)
+    depth[::stride, ::stride] = d[:(cam.height + stride - 1) // stride, :(cam.width + stride - 1) // stride]
+    col[:, ::stride, ::stride] = rgb
+    return Frame(cam, np.asarray(pose, np.float32), depth, col)
+
+
+def serving_sections(seed=4, n_unique=3, kf_per_section=10, width=1200, height=680, stride=2):
+    """Sections of keyframes at width x height for a stride-s map, each along
+    a random walk (validity checked on the stride grid)."""
+    rng = np.random.default_rng(seed)
+    scene = make_room(seed)
+    cam = camera_for(width, height)
+    sub = Camera(cam.fx / stride, cam.fy / stride, cam.cx / stride, cam.cy / stride,
+                 width // stride, height // stride)
+    sections = []
+    for _ in range(n_unique):
+        poses = random_walk(scene, sub, rng, kf_per_section)
+        sections.append([strided_frame(scene, cam, T, stride) for T in poses])
+    return dict(scene=scene, sections=sections, cam=cam, stride=stride)

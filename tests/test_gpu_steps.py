@@ -175,3 +175,44 @@ def test_map_one_iteration(R, orc):
             d_ = (got - old)[sure]
             assert np.all(np.abs(d_ - step_ref[sure]) <= 2e-3 * lr + 2e-6), name
             assert np.all(np.abs(got - old) <= lr * 1.001 + 2e-6), name
+
+
+def test_track_graph_replay_equals_eager(R):
+    """track_step replays a captured graph on a non-default stream; several
+    replays, with eager work and synchronisation between them, give the same
+    poses and losses bit for bit as eager launches."""
+    import os
+    import torch
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1, 160, 120)
+    kf = w["keyframe"]
+    cam = kf.cam.as_tuple()
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, cam, kf.pose)
+    init = torch.tensor(np.asarray(w["init_pose"], np.float32).reshape(12), device="cuda")
+    cfg = R.track_cfg()
+    out = {}
+    for mode in ("eager", "graph"):
+        view = R.View(cam, init.clone(), obs_rgb=kf.rgb, obs_depth=kf.depth).with_pose_adam()
+        plan = R.Plan([k], [view])
+        torch.cuda.synchronize()
+        loss = torch.zeros(8, 1, device="cuda")
+        s = torch.cuda.Stream()
+        res = []
+        with torch.cuda.stream(s):
+            for rep in range(3):
+                view.pose.copy_(init)
+                view.pose_adam.zero_()
+                if mode == "eager":
+                    os.environ["VTGS_NO_GRAPH"] = "1"
+                try:
+                    plan.track_step(cfg, 8, loss)
+                finally:
+                    os.environ.pop("VTGS_NO_GRAPH", None)
+                s.synchronize()
+                res.append((np_(view.pose).copy(), np_(loss).copy()))
+                _ = (view.pose * 2).sum().item()   # unrelated eager work between replays
+        assert plan.status()[0] == 0
+        out[mode] = res
+    for (pe, le), (pg, lg) in zip(out["eager"], out["graph"]):
+        assert np.array_equal(pe, pg) and np.array_equal(le, lg)
+    assert np.array_equal(out["graph"][0][0], out["graph"][2][0])

@@ -138,7 +138,13 @@ def batched_vs_single(iters):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     assert plans[-1].status()[0] == 0
-    del plans, first
+    p = plans[-1]
+    p.timing(True)
+    p.render_fwd()
+    p.render_bwd(g, None, None, twist=False)
+    bstages = {s: v[0] for s, v in p.timing(False).items()}
+    pairs = int(p.debug_state()["n_pairs"].item())
+    del plans, first, p
     # one view per launch
     singles = {i: R.Plan(ks, views_of([i])) for i in range(8)}
     g1 = torch.ones(3, singles[0].P, device="cuda") * 1e-3
@@ -158,7 +164,7 @@ def batched_vs_single(iters):
     return dict(workload="mapping section: 8 keyframes 640x480 (2,457,600 Gaussians), 5 views "
                          "per iteration, fwd+bwd to colour/opacity/radius",
                 iters=iters, batched_mpix_s=px / tb / 1e6, one_view_per_launch_mpix_s=px / ts / 1e6,
-                speedup=ts / tb)
+                speedup=ts / tb, batched_stages_ms=bstages, pairs=pairs)
 
 
 def serving_run(seconds, rate, n_sections, budget_gib, seed=4):

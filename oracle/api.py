@@ -69,7 +69,7 @@ REC_DTYPE = np.dtype([("px", "<f4"), ("py", "<f4"), ("pz", "<f4"), ("mx", "<f4")
 
 class Values(C.Structure):
     _fields_ = [("color", C.c_void_p), ("opacity", C.c_void_p), ("radius", C.c_void_p),
-                ("twist", C.c_double * 6)]
+                ("twist", C.c_double * 6), ("geometry64", C.c_int32)]
 
 
 _lib = None
@@ -178,7 +178,7 @@ def _kf_array(kfs):
     return arr
 
 
-def _values(n, color=None, opacity=None, radius=None, twist=None):
+def _values(n, color=None, opacity=None, radius=None, twist=None, geometry64=False):
     keep = []
     c = o = r = None
     if color is not None:
@@ -188,7 +188,7 @@ def _values(n, color=None, opacity=None, radius=None, twist=None):
     if radius is not None:
         r = _f64(radius); keep.append(r)
     tw = (C.c_double * 6)(*(twist if twist is not None else (0.0,) * 6))
-    return Values(_p(c), _p(o), _p(r), tw), keep
+    return Values(_p(c), _p(o), _p(r), tw, 1 if geometry64 else 0), keep
 
 
 # ----------------------------------------------------------------------------
@@ -256,17 +256,20 @@ def slice_size(view, kfs):
     return int(sum(k.n for k in kfs[view.kf_first:view.kf_first + view.kf_count]))
 
 
-def render(view, kfs, prm=None, margin=4e-6, pixels=None, color=None, opacity=None,
-           radius=None, twist=None):
-    """splat({g}, p) -> RGB [3,P], depth [P], silhouette [P] in FP64 on the
-    FP32 contributor decisions (Sec. 3.3, Eq. 1 / Sec. 3.4, Eq. 2 inputs).
+def render(view, kfs, prm=None, margin=2e-6, pixels=None, color=None, opacity=None,
+           radius=None, twist=None, geometry64=False):
+    """splat({g}, p) -> RGB [3,P], depth [P], silhouette [P]: FP64
+    compositing on the FP32 contributor decisions (Sec. 3.3, Eq. 1 / Sec.
+    3.4, Eq. 2 inputs).  By default the composited mean, conic and depth are
+    those of the pinned FP32 records; geometry64=True recomputes them in FP64
+    (a smooth function of the inputs, for finite differences).
     ``pixels`` selects row-major pixel indices (brute force per pixel)."""
     L = lib()
     prm = prm or params()
     ka = _kf_array(kfs)
     vs = view.cstruct()
     N = slice_size(view, kfs)
-    val, keep = _values(N, color, opacity, radius, twist)
+    val, keep = _values(N, color, opacity, radius, twist, geometry64)
     if pixels is None:
         P, npx, idx = view.P, -1, None
     else:
@@ -283,7 +286,7 @@ def render(view, kfs, prm=None, margin=4e-6, pixels=None, color=None, opacity=No
 
 
 def render_bwd(view, kfs, g_rgb, g_depth=None, g_sil=None, prm=None, color=None,
-               opacity=None, radius=None, twist=None):
+               opacity=None, radius=None, twist=None, geometry64=False):
     """Exact derivative of ``render`` (contributor sets fixed) w.r.t. colour,
     opacity, radius of every Gaussian of the slice and the view twist."""
     L = lib()
@@ -291,7 +294,7 @@ def render_bwd(view, kfs, g_rgb, g_depth=None, g_sil=None, prm=None, color=None,
     ka = _kf_array(kfs)
     vs = view.cstruct()
     N = slice_size(view, kfs)
-    val, keep = _values(N, color, opacity, radius, twist)
+    val, keep = _values(N, color, opacity, radius, twist, geometry64)
     P = view.P
     gr = _f64(np.asarray(g_rgb).reshape(3, P))
     gd = None if g_depth is None else _f64(g_depth)

@@ -207,6 +207,7 @@ typedef struct {
   double dJ[3][2][3];/* d J / d p_k */
   double Q[2][2];    /* inverse of Sigma_2D */
   double r;
+  double z;          /* depth composited into D' */
 } geo64;
 
 static void mat34_mul(const double *A, const double *B, double *C) {
@@ -270,6 +271,7 @@ static void geo_of(const double *M, const orc_cam *kc, const orc_cam *vc, uint32
   g->Q[1][1] = S[0][0] / det;
   g->Q[0][1] = g->Q[1][0] = -S[0][1] / det;
   g->r = r;
+  g->z = z;
 }
 
 /* q, and the pieces of its derivative, at pixel (u, v) */
@@ -333,6 +335,17 @@ static int scene_build(const orc_view *v, const orc_kf *kfs, const orc_params *p
     for (int32_t i = 0; i < k->n; i++, id++) {
       double r = (val && val->radius) ? val->radius[id] : k->radius[i];
       geo_of(M, &k->cam, &v->cam, k->pix[i], k->depth[i], r, prm->lowpass, &s->geo[id]);
+      if (!(val && val->geometry64) && s->rec[id].count > 0) {
+        /* composite the pinned FP32 record: mean, conic, depth */
+        const orc_rec *rc = &s->rec[id];
+        geo64 *g = &s->geo[id];
+        g->mu[0] = rc->mx;
+        g->mu[1] = rc->my;
+        g->Q[0][0] = rc->qa;
+        g->Q[0][1] = g->Q[1][0] = rc->qb;
+        g->Q[1][1] = rc->qc;
+        g->z = rc->pz;
+      }
       for (int c = 0; c < 3; c++)
         s->col[(size_t)c * N + id] = (val && val->color) ? val->color[(size_t)c * N + id]
                                                           : k->color[(int64_t)c * k->n + i];
@@ -508,7 +521,7 @@ static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params 
     double q = q_at(&s->geo[g], x, y, w);
     double a = e[i].clamped ? (double)prm->alpha_max : s->opa[g] * exp(-0.5 * q);
     for (int c = 0; c < 3; c++) C[c] += s->col[(size_t)c * s->N + g] * a * T;
-    *D += s->geo[g].p[2] * a * T;
+    *D += s->geo[g].z * a * T;
     T *= (1.0 - a);
     T32 = Tn;
     u = un;
@@ -619,13 +632,13 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
     double gD = g_depth ? g_depth[p] : 0.0, gS = g_sil ? g_sil[p] : 0.0;
     for (int64_t i = 0; i < k; i++) {
       int32_t g = e[i].id;
-      double z = s.geo[g].p[2];
+      double z = s.geo[g].z;
       /* contributions of everything behind i, summed directly */
       double behindC[3] = {prm->bg[0] * TN, prm->bg[1] * TN, prm->bg[2] * TN}, behindD = 0.0;
       for (int64_t j = i + 1; j < k; j++) {
         int32_t h = e[j].id;
         for (int c = 0; c < 3; c++) behindC[c] += s.col[(size_t)c * N + h] * a[j] * T[j];
-        behindD += s.geo[h].p[2] * a[j] * T[j];
+        behindD += s.geo[h].z * a[j] * T[j];
       }
       double inv = 1.0 / (1.0 - a[i]);
       double dL_da = 0.0;

@@ -71,12 +71,19 @@ typedef struct {
 } orc_rec;
 
 /* Optional FP64 value inputs over the slice's local ids (NULL => the
- * keyframes' float values), plus a left twist applied to the view pose. */
+ * keyframes' float values), plus a left twist applied to the view pose.
+ * geometry64 = 0: the forward composites, in FP64, the projected mean,
+ * conic and depth of the pinned FP32 records (the definition both sides
+ * share bit for bit); derivatives use the FP64 geometry.  geometry64 = 1:
+ * every geometric quantity is recomputed in FP64 from the (overridden)
+ * inputs -- a smooth function of colour, opacity, radius and twist, for
+ * finite differences and closed forms. */
 typedef struct {
   const double *color;     /* [3][N] */
   const double *opacity;   /* [N]    */
   const double *radius;    /* [N]    */
   double twist[6];         /* (rho, phi): pose <- exp(twist^) * pose */
+  int32_t geometry64;
 } orc_values;
 
 /* ---- keyframe ingestion: valid pixels -> compact Gaussian list ---- */

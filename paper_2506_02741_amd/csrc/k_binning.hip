@@ -244,8 +244,83 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
             });
 }
 
+constexpr int kSortCap = 8192;
+
+// Wave-wide inclusive prefix sum of a 64-bit value.
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x) {
+  const int l = lane_id();
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o);
+    if (l >= o) x += y;
+  }
+  return x;
+}
+
+// Stable LSD radix sort of n <= kSortCap 64-bit keys held in LDS (a -> b ->
+// a ...), 2-bit digits, only over bit positions where the keys differ.
+// Each thread owns a contiguous run of keys; per pass it counts its keys per
+// digit into four 16-bit fields of one 64-bit word, a block-wide exclusive
+// scan of those words gives every thread its start in each digit bucket, and
+// the keys are scattered in run order (stable).  Returns the buffer holding
+// the sorted keys.
+__device__ unsigned long long *block_radix_sort(unsigned long long *a, unsigned long long *b,
+                                                int n, unsigned long long *red) {
+  const int t = threadIdx.x, nt = blockDim.x, l = lane_id(), w = t / kWave, nw = nt / kWave;
+  const int per = (n + nt - 1) / nt;
+  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
+  // bits that vary over the keys
+  unsigned long long orv = 0ull, andv = ~0ull;
+  for (int i = i0; i < i1; i++) { orv |= a[i]; andv &= a[i]; }
+  for (int o = 32; o > 0; o >>= 1) {
+    orv |= __shfl_xor(orv, o);
+    andv &= __shfl_xor(andv, o);
+  }
+  if (l == 0) { red[2 * w] = orv; red[2 * w + 1] = andv; }
+  __syncthreads();
+  orv = 0ull; andv = ~0ull;
+  for (int i = 0; i < nw; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
+  const unsigned long long diff = orv ^ andv;
+  __syncthreads();
+  unsigned long long *src = a, *dst = b;
+  for (int bit = 0; bit < 64; bit += 2) {
+    if (((diff >> bit) & 3ull) == 0ull) continue;
+    unsigned long long cnt = 0ull;
+    for (int i = i0; i < i1; i++) cnt += 1ull << (16 * (int)((src[i] >> bit) & 3ull));
+    // block-wide exclusive scan of the packed counts
+    const unsigned long long inc = wave_incl_scan_u64(cnt);
+    if (l == kWave - 1) red[w] = inc;
+    __syncthreads();
+    unsigned long long before = 0ull, total = 0ull;
+    for (int i = 0; i < nw; i++) {
+      const unsigned long long v = red[i];
+      if (i < w) before += v;
+      total += v;
+    }
+    const unsigned long long ex = before + inc - cnt;
+    const uint32_t t0 = (uint32_t)(total & 0xffff), t1 = (uint32_t)((total >> 16) & 0xffff),
+                   t2 = (uint32_t)((total >> 32) & 0xffff);
+    uint32_t off[4] = {(uint32_t)(ex & 0xffff), t0 + (uint32_t)((ex >> 16) & 0xffff),
+                       t0 + t1 + (uint32_t)((ex >> 32) & 0xffff),
+                       t0 + t1 + t2 + (uint32_t)((ex >> 48) & 0xffff)};
+    for (int i = i0; i < i1; i++) {
+      const unsigned long long k = src[i];
+      const int d = (int)((k >> bit) & 3ull);
+      uint32_t pos;
+      if (d == 0) pos = off[0]++;
+      else if (d == 1) pos = off[1]++;
+      else if (d == 2) pos = off[2]++;
+      else pos = off[3]++;
+      dst[pos] = k;
+    }
+    __syncthreads();
+    unsigned long long *tmp = src; src = dst; dst = tmp;
+  }
+  return src;
+}
+
 // Bitonic sort with ascending comparators only (a flip stage then
 // half-cleaners), so indices >= n behave as +infinity and need no padding.
+// Used in global memory for tiles longer than the LDS capacity.
 template <typename T>
 __device__ __forceinline__ void bitonic_sort(T *s, int n) {
   int np = 1;
@@ -256,8 +331,8 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
       const int i = (c / half) * k + (c % half);
       const int p = i + (k - 1 - 2 * (c % half));
       if (p < n) {
-        const auto a = s[i], b = s[p];
-        if (b < a) { s[i] = b; s[p] = a; }
+        const auto x = s[i], y = s[p];
+        if (y < x) { s[i] = y; s[p] = x; }
       }
     }
     __syncthreads();
@@ -266,8 +341,8 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
         const int i = (c / j) * 2 * j + (c % j);
         const int p = i + j;
         if (p < n) {
-          const auto a = s[i], b = s[p];
-          if (b < a) { s[i] = b; s[p] = a; }
+          const auto x = s[i], y = s[p];
+          if (y < x) { s[i] = y; s[p] = x; }
         }
       }
       __syncthreads();
@@ -275,29 +350,39 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
   }
 }
 
-constexpr int kSortCap = 8192;
-__global__ __launch_bounds__(kNT) void k_sort_tiles(Ws ws) {
-  __shared__ unsigned long long s[kSortCap];
+// One block per tile: keys (depth bits << 32 | id) are unique within a tile,
+// so ascending key order is the (depth, id) order.  Each variant handles the
+// tiles whose length lies in (lo_n, hi_n]; longer than CAP -> global memory.
+template <int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
+  __shared__ unsigned long long s[2 * CAP];
+  __shared__ unsigned long long red[2 * (NT / kWave)];
   // ranges are clamped to the capacity, and every position of a clamped
   // range was written by the fill, so sorting stays in bounds on overflow
   const uint2 rg = ws.ranges[blockIdx.x];
   const int n = (int)(rg.y - rg.x);
-  if (n <= 0) return;
+  if (n <= lo_n || n > hi_n || n <= 0) return;
   const unsigned long long *src = ws.keys + rg.x;
   uint32_t *dst = ws.ids + rg.x;
-  if (n <= kSortCap) {
-    for (int i = threadIdx.x; i < n; i += kNT) s[i] = src[i];
+  if (n == 1) {
+    if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
+    return;
+  }
+  if (n <= CAP) {
+    for (int i = threadIdx.x; i < n; i += NT) s[i] = src[i];
     __syncthreads();
-    bitonic_sort(s, n);
-    for (int i = threadIdx.x; i < n; i += kNT) dst[i] = (uint32_t)s[i];
+    const unsigned long long *out = block_radix_sort(s, s + CAP, n, red);
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)out[i];
   } else {
     unsigned long long *g = ws.keys_tmp + rg.x;
-    for (int i = threadIdx.x; i < n; i += kNT) g[i] = src[i];
+    for (int i = threadIdx.x; i < n; i += NT) g[i] = src[i];
     __syncthreads();
     bitonic_sort(g, n);
-    for (int i = threadIdx.x; i < n; i += kNT) dst[i] = (uint32_t)g[i];
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)g[i];
   }
 }
+
+constexpr int kSmallSort = 2048;
 
 // Device-wide exclusive scan of rec_cnt -> rec_off (3 phases).
 constexpr int kRecPer = 8, kRecBlock = kNT * kRecPer;
@@ -398,7 +483,10 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 }
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_sort_tiles, dim3(ws.n_tiles), dim3(kNT), 0, st, ws);
+  hipLaunchKernelGGL((k_sort_tiles<kSmallSort, 256>), dim3(ws.n_tiles), dim3(256), 0, st, ws, 0,
+                     kSmallSort);
+  hipLaunchKernelGGL((k_sort_tiles<kSortCap, 512>), dim3(ws.n_tiles), dim3(512), 0, st, ws,
+                     kSmallSort, 0x7fffffff);
   return hipGetLastError();
 }
 

@@ -164,13 +164,22 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
       if (j + 1 < nb) { n0 = e0s[j + 1]; n1 = e1s[j + 1]; n2 = e2s[j + 1]; }
       if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
       const uint32_t pos = (uint32_t)(b - start + j + 1);
+      float qs[PPT];
+      bool inq[PPT], anyq = false;
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
         float dx, dy;
-        const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+        qs[k] = quad(e0, e1.x, px[k], py[k], dx, dy);
+        inq[k] = !done[k] && (qs[k] <= qcut);
+        anyq = anyq || inq[k];
+      }
+      if (__builtin_amdgcn_readfirstlane((int)(ballot64(anyq) != 0ull)) == 0) continue;
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        const float q = qs[k];
         const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
         const float a = fminf(amax, e1.y * G);
-        const bool ok = !done[k] && (q <= qcut) && (a >= amin);
+        const bool ok = inq[k] && (a >= amin);
         const float Tn = T[k] * (1.0f - a);
         const bool stop = ok && (Tn < tmin);
         const bool take = ok && !stop;
@@ -353,17 +362,21 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
       const int idx = lo + j - start;
       bool ok[PPT];
-      float dxs[PPT], dys[PPT], Gs[PPT], as[PPT];
+      float dxs[PPT], dys[PPT], qs[PPT], Gs[PPT], as[PPT];
       bool any = false;
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
-        const float q = quad(e0, e1.x, px[k], py[k], dxs[k], dys[k]);
-        Gs[k] = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-        as[k] = fminf(amax, e1.y * Gs[k]);
-        ok[k] = (idx < (int)last[k]) && (q <= qcut) && (as[k] >= amin);
+        qs[k] = quad(e0, e1.x, px[k], py[k], dxs[k], dys[k]);
+        ok[k] = (idx < (int)last[k]) && (qs[k] <= qcut);
         any = any || ok[k];
       }
       if (__builtin_amdgcn_readfirstlane((int)(ballot64(any) != 0ull)) == 0) continue;
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        Gs[k] = __builtin_amdgcn_exp2f(qs[k] * kNegHalfLog2e);
+        as[k] = fminf(amax, e1.y * Gs[k]);
+        ok[k] = ok[k] && (as[k] >= amin);
+      }
       float sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, so = 0.f, sr = 0.f;
 #pragma unroll
       for (int k = 0; k < PPT; k++) {

@@ -181,6 +181,10 @@ class Plan:
                  workspace=None, bind=True):
         self.L = load()
         self.keyframes = list(keyframes)
+        # the descriptors capture the gradient buffers: create them first
+        for k in self.keyframes:
+            if k.learnable and k.g_color is None:
+                k.with_grad_buffers()
         self.views = list(views)
         self.prm = prm if prm is not None else params()
         self.device = _dev(device)

@@ -403,3 +403,27 @@ def test_autograd_matches_oracle_and_fd(R, orc):
                 k.opacity[i] -= s * eps
             fd = (vals[0] - vals[1]) / (2 * eps)
             assert abs(fd - float(k.opacity.grad[i])) <= 2e-2 * max(1.0, abs(fd)), (fd, float(k.opacity.grad[i]))
+
+
+@pytest.mark.parametrize("zoom,tile", [(2.5, 16), (4.0, 32), (8.0, 32)])
+def test_long_tile_lists_bitwise(R, orc, zoom, tile):
+    """A zoomed-out view puts several keyframes' Gaussians into few tiles, so
+    tile lists exceed the short-list sort (2048) and, at the largest zoom,
+    the LDS capacity (8192, sorted in global memory)."""
+    cam, frames, vpose = room_frames(9, 96, 72, n_kf=3)
+    ks = [gpu_kf(R, fr) for fr in frames]
+    c = (cam.fx / zoom, cam.fy / zoom, cam.cx, cam.cy, cam.width, cam.height)
+    plan = R.Plan(ks, [R.View(c, vpose, 0, 3)], R.params(tile=tile))
+    imgs = plan.render_fwd()
+    st = plan.debug_state()
+    assert plan.status()[0] == 0
+    okfs = [oracle_kf(orc, f) for f in frames]
+    ov = orc.ViewSpec(c, vpose, 0, 3)
+    prm = orc.params(tile=tile)
+    keys, vals, ranges = orc.tile_lists(ov, okfs, prm)
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert lens.max() > 2048
+    assert np.array_equal(np_(st["ranges"]).astype(np.uint32), ranges)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+    ref = orc.render(ov, okfs, prm, margin=MARGIN)
+    check_images(*imgs, ref, max_marginal=2e-2)

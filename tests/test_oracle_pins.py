@@ -247,7 +247,7 @@ def test_tile_lists_bruteforce(orc, B):
 # ----------------------------------------------------------------------------
 
 def _loss(orc, view, kfs, g, prm, **vals):
-    out = orc.render(view, kfs, prm, margin=0.0, **vals)
+    out = orc.render(view, kfs, prm, margin=0.0, geometry64=True, **vals)
     return float(np.sum(out["rgb"] * g[0]) + np.sum(out["depth"] * g[1]) + np.sum(out["sil"] * g[2]))
 
 
@@ -260,7 +260,7 @@ def test_gradients_finite_differences(orc, thresholds):
     rng = np.random.default_rng(3)
     P = view.P
     g = (rng.normal(size=(3, P)), rng.normal(size=P), rng.normal(size=P))
-    grad = orc.render_bwd(view, [kf], g[0], g[1], g[2], prm)
+    grad = orc.render_bwd(view, [kf], g[0], g[1], g[2], prm, geometry64=True)
     c0 = kf.color.astype(np.float64); o0 = kf.opacity.astype(np.float64); r0 = kf.radius.astype(np.float64)
     picks = rng.choice(kf.n, 6, replace=False)
     for i in picks:
@@ -295,7 +295,7 @@ def test_pose_gradient_closed_form(orc):
     sig2 = (F * r / z) ** 2 + float(np.float32(0.3))
     for du, dv in ((1, 0), (2, 1), (-1, 2)):
         gs = np.zeros(P); gs[(24 + dv) * 64 + 32 + du] = 1.0
-        tw = orc.render_bwd(view, [kf], np.zeros((3, P)), None, gs)["twist"]
+        tw = orc.render_bwd(view, [kf], np.zeros((3, P)), None, gs, geometry64=True)["twist"]
         a = o * math.exp(-(du * du + dv * dv) / (2 * sig2))
         # d alpha / d mu = alpha * d / sigma^2 ; d mu / d p_xy = f / z
         assert abs(tw[0] - a * du / sig2 * F / z) < 1e-9
@@ -312,13 +312,13 @@ def test_rigid_invariance(orc):
     """Moving the whole scene and the camera by one rigid transform changes
     no pixel (the splat depends only on relative poses)."""
     fr, kf, view = small_room(orc, seed=13)
-    out = orc.render(view, [kf])
+    out = orc.render(view, [kf], geometry64=True)
     A = orc.se3_exp(np.array([0.3, -0.2, 0.1, 0.05, -0.1, 0.2]))
     Ainv = np.concatenate([A[:, :3].T, (-A[:, :3].T @ A[:, 3])[:, None]], 1)
     kf2 = orc.Keyframe(kf.cam, orc.compose(kf.pose.reshape(3, 4), Ainv).astype(np.float32), kf.pix,
                        kf.depth, kf.color, kf.opacity, kf.radius)
     v2 = orc.ViewSpec(view.cam, orc.compose(view.pose.reshape(3, 4), Ainv).astype(np.float32))
-    out2 = orc.render(v2, [kf2])
+    out2 = orc.render(v2, [kf2], geometry64=True)
     # the float32 rounding of the moved poses perturbs relative poses by
     # ~1e-7, which can flip a decision at a handful of pixels
     for k in ("depth", "sil"):

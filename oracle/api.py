@@ -96,7 +96,7 @@ def lib():
         L.orc_render_fwd.restype = C.c_int
         L.orc_render_fwd.argtypes = [P, P, P, P, C.c_float, C.c_int32, P, P, P, P, P, P, P]
         L.orc_render_bwd.restype = C.c_int
-        L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_track_loss.restype = C.c_double
         L.orc_track_loss.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_double, C.c_double,
                                      C.c_double, P, P]
@@ -301,11 +301,14 @@ def render_bwd(view, kfs, g_rgb, g_depth=None, g_sil=None, prm=None, color=None,
     gs = None if g_sil is None else _f64(g_sil)
     gc = np.zeros((3, max(N, 1))); go = np.zeros(max(N, 1)); grd = np.zeros(max(N, 1))
     tw = np.zeros(6)
+    mag = np.zeros(5 * N + 6)
     rc = L.orc_render_bwd(C.byref(vs), ka, C.byref(prm), C.byref(val), _p(gr), _p(gd), _p(gs),
-                          _p(gc), _p(go), _p(grd), _p(tw))
+                          _p(gc), _p(go), _p(grd), _p(tw), _p(mag))
     if rc < 0:
         raise MemoryError("oracle backward failed")
-    return dict(color=gc[:, :N], opacity=go[:N], radius=grd[:N], twist=tw)
+    mags = dict(color=mag[:3 * N].reshape(3, N), opacity=mag[3 * N:4 * N],
+                radius=mag[4 * N:5 * N], twist=mag[5 * N:5 * N + 6])
+    return dict(color=gc[:, :N], opacity=go[:N], radius=grd[:N], twist=tw, mag=mags)
 
 
 def track_loss(rgb, depth, sil, obs_rgb, obs_depth, vis=None, alpha=0.5, beta=1.0,

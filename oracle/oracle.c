@@ -588,7 +588,7 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
 int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                    const orc_values *val, const double *g_rgb, const double *g_depth,
                    const double *g_sil, double *g_color, double *g_opac, double *g_rad,
-                   double *g_twist) {
+                   double *g_twist, double *g_mag) {
   scene_t s;
   if (scene_build(v, kfs, prm, val, &s)) return -1;
   lists_t L;
@@ -599,6 +599,11 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
   memset(g_color, 0, sizeof(double) * 3 * (size_t)N);
   memset(g_opac, 0, sizeof(double) * (size_t)N);
   memset(g_rad, 0, sizeof(double) * (size_t)N);
+  double *mag_p = NULL;
+  if (g_mag) {
+    memset(g_mag, 0, sizeof(double) * (5 * (size_t)N + 6));
+    mag_p = (double *)calloc((size_t)(N > 0 ? N : 1) * 3, sizeof(double));
+  }
   int64_t maxn = 0;
   for (int64_t p = 0; p < P; p++)
     if (L.off[p + 1] - L.off[p] > maxn) maxn = L.off[p + 1] - L.off[p];
@@ -658,6 +663,24 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
       g_rad[g] += dL_dq * dq_dr;
       for (int m = 0; m < 3; m++) g_p[3 * g + m] += dL_dq * dq_dp[m];
       g_p[3 * g + 2] += dL_dz;
+      if (g_mag) {
+        /* the same terms with every summand replaced by its absolute value:
+         * the scale against which a rounded evaluation of the sums is judged */
+        double m_da = 0.0;
+        for (int c = 0; c < 3; c++)
+          m_da += fabs(gC[c]) * (fabs(s.col[(size_t)c * N + g]) * T[i] + fabs(behindC[c]) * inv);
+        m_da += fabs(gD) * (fabs(z) * T[i] + fabs(behindD) * inv);
+        m_da += fabs(gS) * (TN * inv);
+        for (int c = 0; c < 3; c++) g_mag[(size_t)c * N + g] += fabs(a[i] * T[i] * gC[c]);
+        double m_dq = 0.0;
+        if (!e[i].clamped) {
+          g_mag[3 * (size_t)N + g] += G[i] * m_da;
+          m_dq = m_da * s.opa[g] * G[i] * 0.5;
+        }
+        g_mag[4 * (size_t)N + g] += m_dq * fabs(dq_dr);
+        for (int m = 0; m < 3; m++) mag_p[3 * g + m] += m_dq * fabs(dq_dp[m]);
+        mag_p[3 * g + 2] += fabs(dL_dz);
+      }
     }
   }
   /* twist (rho, phi) of the left perturbation: dp/drho = I, dp/dphi = -[p]x */
@@ -670,7 +693,18 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
     g_twist[3] += pp[1] * gp[2] - pp[2] * gp[1];
     g_twist[4] += pp[2] * gp[0] - pp[0] * gp[2];
     g_twist[5] += pp[0] * gp[1] - pp[1] * gp[0];
+    if (g_mag) {
+      const double *mp = &mag_p[3 * g];
+      double *mt = g_mag + 5 * (size_t)N;
+      mt[0] += mp[0];
+      mt[1] += mp[1];
+      mt[2] += mp[2];
+      mt[3] += fabs(pp[1]) * mp[2] + fabs(pp[2]) * mp[1];
+      mt[4] += fabs(pp[2]) * mp[0] + fabs(pp[0]) * mp[2];
+      mt[5] += fabs(pp[0]) * mp[1] + fabs(pp[1]) * mp[0];
+    }
   }
+  free(mag_p);
   free(a); free(G); free(T); free(qw); free(g_p);
   lists_free(&L);
   scene_free(&s);

@@ -115,11 +115,15 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
 
 /* ---- backward: exact derivative of the forward with the FP32 contributor
  * sets held fixed.  g_color [3][N], g_opac [N], g_rad [N] over the slice's
- * local ids (overwritten), g_twist [6] (overwritten). ---- */
+ * local ids (overwritten), g_twist [6] (overwritten).  g_mag (NULL or
+ * [5N + 6]: colour, opacity, radius, twist) receives each gradient's sum of
+ * absolute summands -- every per-pixel term, and every product and sum
+ * inside it, taken in absolute value -- the scale of the rounding error of
+ * any evaluation of those sums in a shorter precision. ---- */
 int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                    const orc_values *val, const double *g_rgb, const double *g_depth,
                    const double *g_sil, double *g_color, double *g_opac, double *g_rad,
-                   double *g_twist);
+                   double *g_twist, double *g_mag);
 
 /* ---- losses ---- */
 double orc_track_loss(int32_t P, const double *rgb, const double *depth, const double *sil,

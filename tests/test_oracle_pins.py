@@ -283,6 +283,29 @@ def test_gradients_finite_differences(orc, thresholds):
         assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (k, fd, an)
 
 
+# P7b: the absolute-summand scale of each gradient bounds it, and equals it
+# when every summand has one sign (a single Gaussian, non-negative colour
+# upstream, zero background: each pixel adds a T c g_C >= 0 to the colour
+# gradient and G T c g_C >= 0 to the opacity gradient)
+def test_gradient_magnitudes(orc):
+    fr, kf, view = small_room(orc, seed=11, w=24, h=18)
+    rng = np.random.default_rng(5)
+    P = view.P
+    grad = orc.render_bwd(view, [kf], rng.normal(size=(3, P)), rng.normal(size=P),
+                          rng.normal(size=P))
+    for name in ("color", "opacity", "radius", "twist"):
+        m, g = grad["mag"][name], grad[name]
+        assert np.all(m >= np.abs(g) * (1 - 1e-12)), name
+        assert np.any(m > 2 * np.abs(g)), name      # random upstream does cancel somewhere
+    one = one_gaussian_kf(orc, 32, 24, 2.0, opacity=0.8)
+    v1 = orc.ViewSpec(CAM, IDENT)
+    P1 = 64 * 48
+    g1 = orc.render_bwd(v1, [one], rng.uniform(0.0, 1.0, size=(3, P1)), None, None)
+    assert g1["color"].min() > 0 and g1["opacity"][0] > 0
+    assert np.allclose(g1["mag"]["color"], g1["color"], rtol=1e-12, atol=0)
+    assert np.allclose(g1["mag"]["opacity"], g1["opacity"], rtol=1e-12, atol=0)
+
+
 # P8: pose gradient closed forms for an on-axis Gaussian
 def test_pose_gradient_closed_form(orc):
     z, o = 2.0, 0.8

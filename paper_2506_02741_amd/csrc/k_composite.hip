@@ -2,10 +2,12 @@
 // and its reverse-mode replay.
 //
 // One workgroup per (view, tile).  Each wave owns a square block of the
-// tile (8x8 pixels, or 16x16 for 32-pixel tiles with four pixels per lane);
-// a Gaussian whose extent box misses that block is skipped by the whole
-// wave with a scalar branch.  The tile's depth-sorted list is walked in
-// batches staged through LDS.
+// tile (8x8 pixels, or 16x16 for 32-pixel tiles with four pixels per lane).
+// The tile's depth-sorted list is walked in batches staged through LDS;
+// while staging, the block marks for every wave which entries have an
+// extent box that touches the wave's pixels (one 64-bit mask per wave and
+// 64 entries), and each wave then visits only the set bits of its masks
+// with scalar bit scans, two entries per step.
 //
 // Forward, per pixel, front to back [splat of Sec. 3.3]:
 //   q = d^T Q d with d = pixel - mu; skip q > q_cut
@@ -58,12 +60,38 @@ __device__ __forceinline__ void lane_pixel(int k, int &x, int &y) {
   y = qy + l / 8 + 8 * (k / 2);
 }
 
+// Origin of wave ww's pixel block relative to the tile origin.
 template <int TILE>
-__device__ __forceinline__ void wave_block(int &x0, int &y0) {
-  const int w = threadIdx.x / kWave;
+__device__ __forceinline__ void block_of(int ww, int &x0, int &y0) {
   if (TILE == 8) { x0 = 0; y0 = 0; return; }
-  x0 = (w % 2) * Shape<TILE>::WB;
-  y0 = (w / 2) * Shape<TILE>::WB;
+  x0 = (ww % 2) * Shape<TILE>::WB;
+  y0 = (ww / 2) * Shape<TILE>::WB;
+}
+
+// Wave masks of a staged batch: bit (i % 64) of masks[ww][i / 64] is set
+// when entry i is present and its extent box mu +- R touches wave ww's
+// pixel block.  Called by every lane (the ballot is wave-wide); the lanes of
+// a wave stage 64 consecutive entries, so i / 64 is uniform.
+template <int TILE, int NCH>
+__device__ __forceinline__ void stage_masks(unsigned long long (*masks)[NCH], int i, bool have,
+                                            const float4 &e0, float R, float ox, float oy) {
+  constexpr int NW = Shape<TILE>::NT / kWave, WB = Shape<TILE>::WB;
+#pragma unroll
+  for (int ww = 0; ww < NW; ww++) {
+    int x0, y0;
+    block_of<TILE>(ww, x0, y0);
+    const float bx0 = ox + (float)x0, by0 = oy + (float)y0;
+    const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
+    const bool miss = (e0.x + R < bx0) | (e0.x - R > bx1) | (e0.y + R < by0) | (e0.y - R > by1);
+    const unsigned long long m = ballot64(have && !miss);
+    if (lane_id() == 0) masks[ww][i / kWave] = m;
+  }
+}
+
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // q = d^T Q d in a fixed order (d = pixel - mu).
@@ -75,13 +103,6 @@ __device__ __forceinline__ float quad(const float4 &e0, float qc, float px, floa
   q = fmaf((2.0f * e0.w) * dx, dy, q);
   q = fmaf(qc * dy, dy, q);
   return q;
-}
-
-// Does the extent box mu +- R miss the wave's pixel block?  Scalar branch.
-__device__ __forceinline__ bool wave_skip(const float4 &e0, float R, float bx0, float by0,
-                                          float bx1, float by1) {
-  const bool miss = (e0.x + R < bx0) | (e0.x - R > bx1) | (e0.y + R < by0) | (e0.y - R > by1);
-  return __builtin_amdgcn_readfirstlane((int)miss) != 0;
 }
 
 // Gather entry `id` of the view's records (an id out of range, which a
@@ -101,19 +122,19 @@ __device__ __forceinline__ void load_entry(const Ws &ws, const DevView &vw, uint
 template <int TILE, int BATCH>
 __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, float *out_depth,
                                                          float *out_sil) {
-  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
+  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT;
+  constexpr int NW = NT / kWave;
   constexpr int PER = (BATCH + NT - 1) / NT;  // list entries each thread stages per batch
+  constexpr int NCH = PER * NT / kWave;       // 64-entry chunks of a staged batch
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
+  __shared__ unsigned long long masks[NW][NCH];
   const int t = blockIdx.x;
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
   const int lt = t - vw.tile_base;
   const int ox = (lt % vw.tiles_x) * TILE, oy = (lt / vw.tiles_x) * TILE;
-  int wx0, wy0;
-  wave_block<TILE>(wx0, wy0);
-  const float bx0 = (float)(ox + wx0), by0 = (float)(oy + wy0);
-  const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
   const uint2 rg = ws.ranges[t];
   const int start = (int)rg.x, end = (int)rg.y;
+  const int w = threadIdx.x / kWave;
 
   float px[PPT], py[PPT], T[PPT], C0[PPT], C1[PPT], C2[PPT], D[PPT];
   uint32_t last[PPT];
@@ -129,6 +150,43 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
     T[k] = 1.f; C0[k] = C1[k] = C2[k] = D[k] = 0.f; last[k] = 0;
   }
   const float amin = ws.amin, amax = ws.amax, tmin = ws.tmin, qcut = ws.qcut;
+
+  // one list entry against this lane's pixels; pos = list position + 1
+  auto step = [&](const float4 &e0, const float4 &e1, const float4 &e2, uint32_t pos) {
+    float qs[PPT];
+    bool inq[PPT], anyq = false;
+#pragma unroll
+    for (int k = 0; k < PPT; k++) {
+      float dx, dy;
+      qs[k] = quad(e0, e1.x, px[k], py[k], dx, dy);
+      inq[k] = !done[k] && (qs[k] <= qcut);
+      anyq = anyq || inq[k];
+    }
+    if (ballot64(anyq) == 0ull) return;
+#pragma unroll
+    for (int k = 0; k < PPT; k++) {
+      const float G = __builtin_amdgcn_exp2f(qs[k] * kNegHalfLog2e);
+      const float a = fminf(amax, e1.y * G);
+      const bool ok = inq[k] && (a >= amin);
+      const float Tn = T[k] * (1.0f - a);
+      const bool stop = ok && (Tn < tmin);
+      const bool take = ok && !stop;
+      done[k] = done[k] || stop;
+      const float wgt = take ? a * T[k] : 0.f;
+      C0[k] = fmaf(e2.x, wgt, C0[k]);
+      C1[k] = fmaf(e2.y, wgt, C1[k]);
+      C2[k] = fmaf(e2.z, wgt, C2[k]);
+      D[k] = fmaf(e1.z, wgt, D[k]);
+      T[k] = take ? Tn : T[k];
+      last[k] = take ? pos : last[k];
+    }
+  };
+  auto wave_done = [&]() {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < PPT; k++) all &= done[k];
+    return ballot64(!all) == 0ull;
+  };
 
   // next batch's entries, gathered from global memory into registers while
   // the current batch is composited
@@ -148,7 +206,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
-      if (i < nb) { e0s[i] = p0[k]; e1s[i] = p1[k]; e2s[i] = p2[k]; }
+      const bool have = i < nb;
+      if (have) { e0s[i] = p0[k]; e1s[i] = p1[k]; e2s[i] = p2[k]; }
+      stage_masks<TILE, NCH>(masks, i, have, p0[k], p1[k].w, (float)ox, (float)oy);
     }
     __syncthreads();
     const int nx = b + BATCH;
@@ -157,46 +217,24 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
       const int i = threadIdx.x + k * NT;
       if (i < BATCH && nx + i < end) load_entry(ws, vw, ws.ids[nx + i], p0[k], p1[k], p2[k]);
     }
-    if (__builtin_amdgcn_readfirstlane((int)(ballot64(!mine) != 0ull)) == 0) continue;
-    float4 n0 = e0s[0], n1 = e1s[0], n2 = e2s[0];
-    for (int j = 0; j < nb; j++) {
-      const float4 e0 = n0, e1 = n1, e2 = n2;
-      if (j + 1 < nb) { n0 = e0s[j + 1]; n1 = e1s[j + 1]; n2 = e2s[j + 1]; }
-      if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
-      const uint32_t pos = (uint32_t)(b - start + j + 1);
-      float qs[PPT];
-      bool inq[PPT], anyq = false;
-#pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        float dx, dy;
-        qs[k] = quad(e0, e1.x, px[k], py[k], dx, dy);
-        inq[k] = !done[k] && (qs[k] <= qcut);
-        anyq = anyq || inq[k];
-      }
-      if (__builtin_amdgcn_readfirstlane((int)(ballot64(anyq) != 0ull)) == 0) continue;
-#pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        const float q = qs[k];
-        const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-        const float a = fminf(amax, e1.y * G);
-        const bool ok = inq[k] && (a >= amin);
-        const float Tn = T[k] * (1.0f - a);
-        const bool stop = ok && (Tn < tmin);
-        const bool take = ok && !stop;
-        done[k] = done[k] || stop;
-        const float wgt = take ? a * T[k] : 0.f;
-        C0[k] = fmaf(e2.x, wgt, C0[k]);
-        C1[k] = fmaf(e2.y, wgt, C1[k]);
-        C2[k] = fmaf(e2.z, wgt, C2[k]);
-        D[k] = fmaf(e1.z, wgt, D[k]);
-        T[k] = take ? Tn : T[k];
-        last[k] = take ? pos : last[k];
-      }
-      if ((j & 31) == 31) {
-        bool all = true;
-#pragma unroll
-        for (int k = 0; k < PPT; k++) all &= done[k];
-        if (__builtin_amdgcn_readfirstlane((int)(ballot64(!all) != 0ull)) == 0) break;
+    if (wave_done()) continue;
+    const uint32_t base = (uint32_t)(b - start + 1);
+    int visited = 0;
+    bool finished = false;
+    for (int c = 0; c * kWave < nb && !finished; c++) {
+      unsigned long long m = uniform_u64(masks[w][c]);
+      while (m) {
+        const int ja = c * kWave + __builtin_ctzll(m);
+        m &= m - 1;
+        const bool hb = m != 0ull;
+        const int jb = hb ? c * kWave + __builtin_ctzll(m) : ja;
+        if (hb) m &= m - 1;
+        const float4 a0 = e0s[ja], a1 = e1s[ja], a2 = e2s[ja];
+        const float4 b0 = e0s[jb], b1 = e1s[jb], b2 = e2s[jb];
+        step(a0, a1, a2, base + (uint32_t)ja);
+        if (hb) step(b0, b1, b2, base + (uint32_t)jb);
+        visited += 2;
+        if ((visited & 31) == 0 && wave_done()) { finished = true; break; }
       }
     }
   }
@@ -253,9 +291,10 @@ template <int TILE, int BATCH, int MODE>
 __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_rgb,
                                                          const float *g_depth,
                                                          const float *g_sil) {
-  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT, WB = Shape<TILE>::WB;
+  constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT;
   constexpr int NW = NT / kWave;
   constexpr int PER = (BATCH + NT - 1) / NT;
+  constexpr int NCH = PER * NT / kWave;
   constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
   constexpr int AB = kSlots ? BATCH : 1;
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
@@ -265,16 +304,13 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   __shared__ float acc[NW][5][AB];
   __shared__ int maxlast_s;
   __shared__ float red_s[NW][6];
+  __shared__ unsigned long long masks[NW][NCH];
 
   const int t = blockIdx.x;
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
   const int lt = t - vw.tile_base;
   const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
   const int ox = tx * TILE, oy = ty * TILE;
-  int wx0, wy0;
-  wave_block<TILE>(wx0, wy0);
-  const float bx0 = (float)(ox + wx0), by0 = (float)(oy + wy0);
-  const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
   const uint2 rg = ws.ranges[t];
   const int start = (int)rg.x, end = (int)rg.y;
   const int64_t P = ws.P;
@@ -308,6 +344,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   atomicMax(&maxlast_s, (int)mylast);
   __syncthreads();
   const int stop = start + maxlast_s;
+  // this wave's own last contributor: entries past it touch none of its lanes
+  const int wstop = start + __builtin_amdgcn_readfirstlane(wave_max_i((int)mylast));
 
   float tw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const float amin = ws.amin, amax = ws.amax, qcut = ws.qcut;
@@ -330,6 +368,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
+      stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.w, (float)ox, (float)oy);
       if (i >= nb) continue;
       const BwdEntry &E = st[k];
       e0s[i] = E.e0; e1s[i] = E.e1; e2s[i] = E.e2;
@@ -353,13 +392,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
         if (i < BATCH && nlo + i < lo) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
       }
     }
-    float4 n0 = e0s[nb - 1], n1 = e1s[nb - 1], n2 = e2s[nb - 1], nj = ejs[nb - 1], np = eps_[nb - 1];
-    for (int j = nb - 1; j >= 0; j--) {
-      const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
-      if (j > 0) {
-        n0 = e0s[j - 1]; n1 = e1s[j - 1]; n2 = e2s[j - 1]; nj = ejs[j - 1]; np = eps_[j - 1];
-      }
-      if (wave_skip(e0, e1.w, bx0, by0, bx1, by1)) continue;
+    // one staged entry (batch position j) against this lane's pixels
+    auto step = [&](int j) {
+      const float4 e0 = e0s[j], e1 = e1s[j], e2 = e2s[j], ej = ejs[j], ep = eps_[j];
       const int idx = lo + j - start;
       bool ok[PPT];
       float dxs[PPT], dys[PPT], qs[PPT], Gs[PPT], as[PPT];
@@ -370,7 +405,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
         ok[k] = (idx < (int)last[k]) && (qs[k] <= qcut);
         any = any || ok[k];
       }
-      if (__builtin_amdgcn_readfirstlane((int)(ballot64(any) != 0ull)) == 0) continue;
+      if (ballot64(any) == 0ull) return;
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
         Gs[k] = __builtin_amdgcn_exp2f(qs[k] * kNegHalfLog2e);
@@ -431,6 +466,22 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           acc[w][0][j] = r0; acc[w][1][j] = r1; acc[w][2][j] = r2;
           acc[w][3][j] = r3; acc[w][4][j] = r4;
         }
+      }
+    };
+    // this wave's entries, last to first, below its own last contributor
+    const int lim = min(nb, wstop - lo);
+    for (int c = (lim - 1) / kWave; lim > 0 && c >= 0; c--) {
+      unsigned long long m = uniform_u64(masks[w][c]);
+      const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
+      if (top < kWave) m &= (1ull << top) - 1ull;
+      while (m) {
+        const int ja = 63 - __builtin_clzll(m);
+        m &= ~(1ull << ja);
+        step(c * kWave + ja);
+        if (!m) break;
+        const int jb = 63 - __builtin_clzll(m);
+        m &= ~(1ull << jb);
+        step(c * kWave + jb);
       }
     }
     if (kSlots) {

@@ -460,11 +460,13 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
         }
       }
       if (kSlots && ep.w != 0.f) {
-        const float r0 = wave_sum(sc0), r1 = wave_sum(sc1), r2 = wave_sum(sc2);
-        const float r3 = wave_sum(so), r4 = wave_sum(sr);
-        if (lane_id() == 0) {
-          acc[w][0][j] = r0; acc[w][1][j] = r1; acc[w][2][j] = r2;
-          acc[w][3][j] = r3; acc[w][4][j] = r4;
+        float rt, r4;
+        wave_sum5(sc0, sc1, sc2, so, sr, rt, r4);
+        const int l = lane_id();
+        if ((l & 15) == 0) {
+          const int row = l >> 4;  // rows hold the sums of (c0, c2, c1, opacity)
+          acc[w][row == 1 ? 2 : row == 2 ? 1 : row][j] = rt;
+          if (row == 0) acc[w][4][j] = r4;
         }
       }
     };

@@ -240,8 +240,8 @@ def main():
     ap.add_argument("--batched-iters", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run one 256 MiB device-to-device copy (a kernel of known traffic "
-                         "for scaling hardware byte counters)")
+                    help="also run one elementwise kernel that reads and writes 256 MiB (known "
+                         "traffic for scaling hardware byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-sections", type=int, default=30)
@@ -295,10 +295,11 @@ def main():
     dom = max(stages, key=lambda s: stages[s][0])
 
     if args.calib_copy:
+        # an elementwise kernel that reads 256 MiB and writes 256 MiB
         a = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
 

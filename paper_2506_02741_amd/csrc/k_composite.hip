@@ -151,36 +151,6 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
   }
   const float amin = ws.amin, amax = ws.amax, tmin = ws.tmin, qcut = ws.qcut;
 
-  // one list entry against this lane's pixels; pos = list position + 1
-  auto step = [&](const float4 &e0, const float4 &e1, const float4 &e2, uint32_t pos) {
-    float qs[PPT];
-    bool inq[PPT], anyq = false;
-#pragma unroll
-    for (int k = 0; k < PPT; k++) {
-      float dx, dy;
-      qs[k] = quad(e0, e1.x, px[k], py[k], dx, dy);
-      inq[k] = !done[k] && (qs[k] <= qcut);
-      anyq = anyq || inq[k];
-    }
-    if (ballot64(anyq) == 0ull) return;
-#pragma unroll
-    for (int k = 0; k < PPT; k++) {
-      const float G = __builtin_amdgcn_exp2f(qs[k] * kNegHalfLog2e);
-      const float a = fminf(amax, e1.y * G);
-      const bool ok = inq[k] && (a >= amin);
-      const float Tn = T[k] * (1.0f - a);
-      const bool stop = ok && (Tn < tmin);
-      const bool take = ok && !stop;
-      done[k] = done[k] || stop;
-      const float wgt = take ? a * T[k] : 0.f;
-      C0[k] = fmaf(e2.x, wgt, C0[k]);
-      C1[k] = fmaf(e2.y, wgt, C1[k]);
-      C2[k] = fmaf(e2.z, wgt, C2[k]);
-      D[k] = fmaf(e1.z, wgt, D[k]);
-      T[k] = take ? Tn : T[k];
-      last[k] = take ? pos : last[k];
-    }
-  };
   auto wave_done = [&]() {
     bool all = true;
 #pragma unroll
@@ -219,23 +189,55 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
     }
     if (wave_done()) continue;
     const uint32_t base = (uint32_t)(b - start + 1);
-    int visited = 0;
-    bool finished = false;
-    for (int c = 0; c * kWave < nb && !finished; c++) {
+    for (int c = 0; c * kWave < nb; c++) {
       unsigned long long m = uniform_u64(masks[w][c]);
+      if (m == 0ull) continue;
+      // 1. which of the chunk's entries reach each of this lane's pixels
+      unsigned long long own[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; k++) own[k] = 0ull;
       while (m) {
-        const int ja = c * kWave + __builtin_ctzll(m);
+        const int j = __builtin_ctzll(m);
         m &= m - 1;
-        const bool hb = m != 0ull;
-        const int jb = hb ? c * kWave + __builtin_ctzll(m) : ja;
-        if (hb) m &= m - 1;
-        const float4 a0 = e0s[ja], a1 = e1s[ja], a2 = e2s[ja];
-        const float4 b0 = e0s[jb], b1 = e1s[jb], b2 = e2s[jb];
-        step(a0, a1, a2, base + (uint32_t)ja);
-        if (hb) step(b0, b1, b2, base + (uint32_t)jb);
-        visited += 2;
-        if ((visited & 31) == 0 && wave_done()) { finished = true; break; }
+        const float4 e0 = e0s[c * kWave + j];
+        const float qc = e1s[c * kWave + j].x;
+#pragma unroll
+        for (int k = 0; k < PPT; k++) {
+          float dx, dy;
+          const float q = quad(e0, qc, px[k], py[k], dx, dy);
+          own[k] |= (!done[k] && q <= qcut) ? (1ull << j) : 0ull;
+        }
       }
+      // 2. each lane composites its own entries in list order
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        unsigned long long bits = own[k];
+        const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        for (int n = 0; n < steps; n++) {
+          const bool have = bits != 0ull;
+          const int i = c * kWave + (have ? __builtin_ctzll(bits) : 0);
+          bits &= bits - 1ull;
+          const float4 e0 = e0s[i], e1 = e1s[i], e2 = e2s[i];
+          float dx, dy;
+          const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+          const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+          const float a = fminf(amax, e1.y * G);
+          const bool ok = have && (a >= amin);
+          const float Tn = T[k] * (1.0f - a);
+          const bool stop = ok && (Tn < tmin);
+          const bool take = ok && !stop;
+          done[k] = done[k] || stop;
+          bits = stop ? 0ull : bits;
+          const float wgt = take ? a * T[k] : 0.f;
+          C0[k] = fmaf(e2.x, wgt, C0[k]);
+          C1[k] = fmaf(e2.y, wgt, C1[k]);
+          C2[k] = fmaf(e2.z, wgt, C2[k]);
+          D[k] = fmaf(e1.z, wgt, D[k]);
+          T[k] = take ? Tn : T[k];
+          last[k] = take ? base + (uint32_t)i : last[k];
+        }
+      }
+      if (wave_done()) break;
     }
   }
   const int64_t P = ws.P;
@@ -476,14 +478,85 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       unsigned long long m = uniform_u64(masks[w][c]);
       const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
       if (top < kWave) m &= (1ull << top) - 1ull;
+      if (kSlots) {
+        // slot sums need every lane on the same entry
+        while (m) {
+          const int ja = 63 - __builtin_clzll(m);
+          m &= ~(1ull << ja);
+          step(c * kWave + ja);
+          if (!m) break;
+          const int jb = 63 - __builtin_clzll(m);
+          m &= ~(1ull << jb);
+          step(c * kWave + jb);
+        }
+        continue;
+      }
+      if (m == 0ull) continue;
+      // 1. which of the chunk's entries each of this lane's pixels composited
+      unsigned long long own[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; k++) own[k] = 0ull;
       while (m) {
-        const int ja = 63 - __builtin_clzll(m);
-        m &= ~(1ull << ja);
-        step(c * kWave + ja);
-        if (!m) break;
-        const int jb = 63 - __builtin_clzll(m);
-        m &= ~(1ull << jb);
-        step(c * kWave + jb);
+        const int j = __builtin_ctzll(m);
+        m &= m - 1;
+        const float4 e0 = e0s[c * kWave + j];
+        const float qc = e1s[c * kWave + j].x;
+        const int idx = lo + c * kWave + j - start;
+#pragma unroll
+        for (int k = 0; k < PPT; k++) {
+          float dx, dy;
+          const float q = quad(e0, qc, px[k], py[k], dx, dy);
+          own[k] |= (idx < (int)last[k] && q <= qcut) ? (1ull << j) : 0ull;
+        }
+      }
+      // 2. each lane replays its own entries, last to first
+#pragma unroll
+      for (int k = 0; k < PPT; k++) {
+        unsigned long long bits = own[k];
+        const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        for (int n = 0; n < steps; n++) {
+          const bool have = bits != 0ull;
+          const int jj = have ? 63 - __builtin_clzll(bits) : 0;
+          bits &= have ? ~(1ull << jj) : ~0ull;
+          const int i = c * kWave + jj;
+          const float4 e0 = e0s[i], e1 = e1s[i], e2 = e2s[i], ej = ejs[i], ep = eps_[i];
+          float dx, dy;
+          const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+          const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+          const float a = fminf(amax, e1.y * G);
+          const bool ok = have && (a >= amin);
+          const float oG = e1.y * G;
+          const float om = 1.0f - a;
+          const float Tk = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
+          T[k] = Tk;
+          const float wgt = ok ? a * Tk : 0.f;
+          float dLda = gC0[k] * (e2.x - BC0[k]);
+          dLda = fmaf(gC1[k], e2.y - BC1[k], dLda);
+          dLda = fmaf(gC2[k], e2.z - BC2[k], dLda);
+          dLda = fmaf(gD[k], e1.z - BD[k], dLda);
+          dLda = fmaf(gS[k], 1.0f - BS[k], dLda);
+          dLda = ok ? dLda * Tk : 0.f;
+          BC0[k] = ok ? fmaf(a, e2.x, om * BC0[k]) : BC0[k];
+          BC1[k] = ok ? fmaf(a, e2.y, om * BC1[k]) : BC1[k];
+          BC2[k] = ok ? fmaf(a, e2.z, om * BC2[k]) : BC2[k];
+          BD[k] = ok ? fmaf(a, e1.z, om * BD[k]) : BD[k];
+          BS[k] = ok ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
+          const bool pass = oG <= amax;
+          const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
+          const float qb = e0.w;
+          const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
+          const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
+          const float kk = ep.z;
+          const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
+          const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
+          const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
+          const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+          const float pz = e1.z;
+          tw[0] += g0; tw[1] += g1; tw[2] += g2;
+          tw[3] += ep.y * g2 - pz * g1;
+          tw[4] += pz * g0 - ep.x * g2;
+          tw[5] += ep.x * g1 - ep.y * g0;
+        }
       }
     }
     if (kSlots) {

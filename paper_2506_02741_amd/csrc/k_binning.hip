@@ -246,31 +246,43 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
 
 constexpr int kSortCap = 8192;
 
-// Wave-wide inclusive prefix sum of a 64-bit value.
-__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long x) {
-  const int l = lane_id();
-  for (int o = 1; o < kWave; o <<= 1) {
-    const unsigned long long y = __shfl_up(x, o);
-    if (l >= o) x += y;
-  }
+// Wave-wide inclusive prefix sum of a u32 (DPP row_shr 1, 2, 4, 8 within
+// rows, then row_bcast:15 and row_bcast:31 across rows).  Packed 16-bit
+// fields scan independently while no field total exceeds 0xffff.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
   return x;
 }
 
-// Stable LSD radix sort of n <= kSortCap 64-bit keys held in LDS (a -> b ->
-// a ...), 2-bit digits, only over bit positions where the keys differ.
-// Each thread owns a contiguous run of keys; per pass it counts its keys per
-// digit into four 16-bit fields of one 64-bit word, a block-wide exclusive
-// scan of those words gives every thread its start in each digit bucket, and
-// the keys are scattered in run order (stable).  Returns the buffer holding
-// the sorted keys.
-__device__ unsigned long long *block_radix_sort(unsigned long long *a, unsigned long long *b,
-                                                int n, unsigned long long *red) {
-  const int t = threadIdx.x, nt = blockDim.x, l = lane_id(), w = t / kWave, nw = nt / kWave;
-  const int per = (n + nt - 1) / nt;
-  const int i0 = min(n, t * per), i1 = min(n, i0 + per);
-  // bits that vary over the keys
+// 8-bit field d (0..15) of the pair (lo: fields 0-7, hi: fields 8-15).
+__device__ __forceinline__ uint32_t field8(unsigned long long lo, unsigned long long hi, int d) {
+  const unsigned long long v = d < 8 ? lo : hi;
+  return (uint32_t)(v >> (8 * (d & 7))) & 0xffu;
+}
+
+// Stable LSD radix sort of the NT * E keys of a block, 4-bit digits, only
+// over the digits where the first n keys differ (keys past n must be
+// ~0ull; being maximal and last they stay last).  Thread t holds keys
+// t*E .. t*E+E-1 in registers ("blocked" order).  Per pass each thread
+// counts its keys per digit in 8-bit fields, a DPP wave scan of the counts
+// (as 16-bit fields) and a pass over the wave totals in LDS give each thread
+// its start in every digit bucket, and the keys are scattered through `buf`
+// in thread-then-register order, which keeps the sort stable.  On return
+// buf[0 .. NT*E) holds the sorted keys.
+template <int NT, int E>
+__device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long long *buf,
+                               uint32_t (*wsum)[8], unsigned long long *red) {
+  constexpr int NW = NT / kWave;
+  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
   unsigned long long orv = 0ull, andv = ~0ull;
-  for (int i = i0; i < i1; i++) { orv |= a[i]; andv &= a[i]; }
+#pragma unroll
+  for (int e = 0; e < E; e++)
+    if (t * E + e < n) { orv |= k[e]; andv &= k[e]; }
   for (int o = 32; o > 0; o >>= 1) {
     orv |= __shfl_xor(orv, o);
     andv &= __shfl_xor(andv, o);
@@ -278,44 +290,82 @@ __device__ unsigned long long *block_radix_sort(unsigned long long *a, unsigned 
   if (l == 0) { red[2 * w] = orv; red[2 * w + 1] = andv; }
   __syncthreads();
   orv = 0ull; andv = ~0ull;
-  for (int i = 0; i < nw; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
+#pragma unroll
+  for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
   const unsigned long long diff = orv ^ andv;
-  __syncthreads();
-  unsigned long long *src = a, *dst = b;
-  for (int bit = 0; bit < 64; bit += 2) {
-    if (((diff >> bit) & 3ull) == 0ull) continue;
-    unsigned long long cnt = 0ull;
-    for (int i = i0; i < i1; i++) cnt += 1ull << (16 * (int)((src[i] >> bit) & 3ull));
-    // block-wide exclusive scan of the packed counts
-    const unsigned long long inc = wave_incl_scan_u64(cnt);
-    if (l == kWave - 1) red[w] = inc;
+  int last_shift = -1;
+  for (int sh = 0; sh < 64; sh += 4)
+    if ((diff >> sh) & 15ull) last_shift = sh;
+  if (last_shift < 0) {  // nothing to order
+#pragma unroll
+    for (int e = 0; e < E; e++) buf[t * E + e] = k[e];
     __syncthreads();
-    unsigned long long before = 0ull, total = 0ull;
-    for (int i = 0; i < nw; i++) {
-      const unsigned long long v = red[i];
-      if (i < w) before += v;
-      total += v;
-    }
-    const unsigned long long ex = before + inc - cnt;
-    const uint32_t t0 = (uint32_t)(total & 0xffff), t1 = (uint32_t)((total >> 16) & 0xffff),
-                   t2 = (uint32_t)((total >> 32) & 0xffff);
-    uint32_t off[4] = {(uint32_t)(ex & 0xffff), t0 + (uint32_t)((ex >> 16) & 0xffff),
-                       t0 + t1 + (uint32_t)((ex >> 32) & 0xffff),
-                       t0 + t1 + t2 + (uint32_t)((ex >> 48) & 0xffff)};
-    for (int i = i0; i < i1; i++) {
-      const unsigned long long k = src[i];
-      const int d = (int)((k >> bit) & 3ull);
-      uint32_t pos;
-      if (d == 0) pos = off[0]++;
-      else if (d == 1) pos = off[1]++;
-      else if (d == 2) pos = off[2]++;
-      else pos = off[3]++;
-      dst[pos] = k;
-    }
-    __syncthreads();
-    unsigned long long *tmp = src; src = dst; dst = tmp;
+    return;
   }
-  return src;
+  for (int sh = 0; sh <= last_shift; sh += 4) {
+    if (((diff >> sh) & 15ull) == 0ull) continue;
+    int dg[E];
+    unsigned long long clo = 0ull, chi = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = (int)((k[e] >> sh) & 15ull);
+      dg[e] = d;
+      const unsigned long long one = 1ull << (8 * (d & 7));
+      clo += d < 8 ? one : 0ull;
+      chi += d < 8 ? 0ull : one;
+    }
+    // counts as 16-bit fields: c[q] holds digits 2q and 2q + 1
+    uint32_t c[8], inc[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      c[q] = field8(clo, chi, 2 * q) | (field8(clo, chi, 2 * q + 1) << 16);
+      inc[q] = wave_incl_scan_u32(c[q]);
+    }
+    if (l == kWave - 1) {
+#pragma unroll
+      for (int q = 0; q < 8; q++) wsum[w][q] = inc[q];
+    }
+    __syncthreads();
+    uint32_t start[8], tot[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) { start[q] = inc[q] - c[q]; tot[q] = 0u; }
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const uint32_t v = wsum[i][q];
+        start[q] += i < w ? v : 0u;
+        tot[q] += v;
+      }
+    }
+    uint32_t run = 0u;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const uint32_t a = tot[q] & 0xffffu, b = tot[q] >> 16;
+      start[q] += run | ((run + a) << 16);
+      run += a + b;
+    }
+    unsigned long long slo = 0ull, shi = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = dg[e];
+      uint32_t v = start[0];
+#pragma unroll
+      for (int q = 1; q < 8; q++) v = (d >> 1) == q ? start[q] : v;
+      const uint32_t pos = ((v >> (16 * (d & 1))) & 0xffffu) + field8(slo, shi, d);
+      const unsigned long long one = 1ull << (8 * (d & 7));
+      slo += d < 8 ? one : 0ull;
+      shi += d < 8 ? 0ull : one;
+      buf[min(pos, (uint32_t)(NT * E - 1))] = k[e];  // a permutation of 0 .. NT*E-1
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; e++) k[e] = buf[t * E + e];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; e++) buf[t * E + e] = k[e];
+  __syncthreads();
 }
 
 // Bitonic sort with ascending comparators only (a flip stage then
@@ -352,10 +402,12 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
 
 // One block per tile: keys (depth bits << 32 | id) are unique within a tile,
 // so ascending key order is the (depth, id) order.  Each variant handles the
-// tiles whose length lies in (lo_n, hi_n]; longer than CAP -> global memory.
-template <int CAP, int NT>
+// tiles whose length lies in (lo_n, hi_n]; longer than NT * E -> global memory.
+template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
-  __shared__ unsigned long long s[2 * CAP];
+  constexpr int CAP = NT * E;
+  __shared__ unsigned long long buf[CAP];
+  __shared__ uint32_t wsum[NT / kWave][8];
   __shared__ unsigned long long red[2 * (NT / kWave)];
   // ranges are clamped to the capacity, and every position of a clamped
   // range was written by the fill, so sorting stays in bounds on overflow
@@ -369,10 +421,14 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
     return;
   }
   if (n <= CAP) {
-    for (int i = threadIdx.x; i < n; i += NT) s[i] = src[i];
-    __syncthreads();
-    const unsigned long long *out = block_radix_sort(s, s + CAP, n, red);
-    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)out[i];
+    unsigned long long k[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int i = threadIdx.x * E + e;
+      k[e] = i < n ? src[i] : ~0ull;
+    }
+    block_sort_u64<NT, E>(k, n, buf, wsum, red);
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
   } else {
     unsigned long long *g = ws.keys_tmp + rg.x;
     for (int i = threadIdx.x; i < n; i += NT) g[i] = src[i];
@@ -483,9 +539,9 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 }
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
-  hipLaunchKernelGGL((k_sort_tiles<kSmallSort, 256>), dim3(ws.n_tiles), dim3(256), 0, st, ws, 0,
-                     kSmallSort);
-  hipLaunchKernelGGL((k_sort_tiles<kSortCap, 512>), dim3(ws.n_tiles), dim3(512), 0, st, ws,
+  hipLaunchKernelGGL((k_sort_tiles<256, kSmallSort / 256>), dim3(ws.n_tiles), dim3(256), 0, st,
+                     ws, 0, kSmallSort);
+  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(ws.n_tiles), dim3(512), 0, st, ws,
                      kSmallSort, 0x7fffffff);
   return hipGetLastError();
 }

@@ -420,7 +420,17 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
     return;
   }
-  if (n <= CAP) {
+  if (n <= CAP / 2) {
+    // half the registers per thread when half the capacity suffices
+    unsigned long long k[E / 2];
+#pragma unroll
+    for (int e = 0; e < E / 2; e++) {
+      const int i = threadIdx.x * (E / 2) + e;
+      k[e] = i < n ? src[i] : ~0ull;
+    }
+    block_sort_u64<NT, E / 2>(k, n, buf, wsum, red);
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
+  } else if (n <= CAP) {
     unsigned long long k[E];
 #pragma unroll
     for (int e = 0; e < E; e++) {

@@ -105,6 +105,16 @@ __device__ __forceinline__ float quad(const float4 &e0, float qc, float px, floa
   return q;
 }
 
+// The same q from a staged entry whose off-diagonal term is already
+// doubled (e0.w = 2 qb): identical operations, identical bits.
+__device__ __forceinline__ float quad2(const float4 &e0, float qc, float px, float py) {
+  const float dx = px - e0.x, dy = py - e0.y;
+  float q = (e0.z * dx) * dx;
+  q = fmaf(e0.w * dx, dy, q);
+  q = fmaf(qc * dy, dy, q);
+  return q;
+}
+
 // Gather entry `id` of the view's records (an id out of range, which a
 // consistent list never holds, yields an entry that every wave skips).
 __device__ __forceinline__ void load_entry(const Ws &ws, const DevView &vw, uint32_t id,
@@ -177,7 +187,11 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
       const bool have = i < nb;
-      if (have) { e0s[i] = p0[k]; e1s[i] = p1[k]; e2s[i] = p2[k]; }
+      // the off-diagonal conic term is staged doubled (exact in FP32)
+      if (have) {
+        e0s[i] = make_float4(p0[k].x, p0[k].y, p0[k].z, 2.0f * p0[k].w);
+        e1s[i] = p1[k]; e2s[i] = p2[k];
+      }
       stage_masks<TILE, NCH>(masks, i, have, p0[k], p1[k].w, (float)ox, (float)oy);
     }
     __syncthreads();
@@ -193,33 +207,51 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
       unsigned long long m = uniform_u64(masks[w][c]);
       if (m == 0ull) continue;
       // 1. which of the chunk's entries reach each of this lane's pixels
-      unsigned long long own[PPT];
+      // bits 0-31 and 32-63 of the chunk in two words; entry j is uniform,
+      // so the half it lands in is a scalar choice
+      uint32_t own_lo[PPT], own_hi[PPT];
 #pragma unroll
-      for (int k = 0; k < PPT; k++) own[k] = 0ull;
-      while (m) {
-        const int j = __builtin_ctzll(m);
-        m &= m - 1;
-        const float4 e0 = e0s[c * kWave + j];
-        const float qc = e1s[c * kWave + j].x;
+      for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
+      for (int h = 0; h < 2; h++) {
+        uint32_t mh = (uint32_t)(m >> (32 * h));
+        while (mh) {  // two entries per step, both loads issued first
+          const int ja = __builtin_ctz(mh);
+          mh &= mh - 1u;
+          const bool hb = mh != 0u;
+          const int jb = hb ? __builtin_ctz(mh) : ja;
+          mh &= hb ? mh - 1u : mh;
+          const int ia = c * kWave + 32 * h + ja, ib = c * kWave + 32 * h + jb;
+          const float4 a0 = e0s[ia], b0 = e0s[ib];
+          const float aq = e1s[ia].x, bq = e1s[ib].x;
 #pragma unroll
-        for (int k = 0; k < PPT; k++) {
-          float dx, dy;
-          const float q = quad(e0, qc, px[k], py[k], dx, dy);
-          own[k] |= (!done[k] && q <= qcut) ? (1ull << j) : 0ull;
+          for (int k = 0; k < PPT; k++) {
+            const float qa = quad2(a0, aq, px[k], py[k]);
+            const float qb = quad2(b0, bq, px[k], py[k]);
+            const uint32_t bits = ((!done[k] && qa <= qcut) ? (1u << ja) : 0u) |
+                                  ((!done[k] && qb <= qcut) ? (1u << jb) : 0u);
+            if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
+          }
         }
       }
+      unsigned long long own[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; k++) own[k] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
       // 2. each lane composites its own entries in list order
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
         unsigned long long bits = own[k];
         const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        // the next entry's LDS reads are issued before this one is composited
+        int i = c * kWave + (bits != 0ull ? __builtin_ctzll(bits) : 0);
+        float4 n0 = e0s[i], n1 = e1s[i], n2 = e2s[i];
         for (int n = 0; n < steps; n++) {
           const bool have = bits != 0ull;
-          const int i = c * kWave + (have ? __builtin_ctzll(bits) : 0);
           bits &= bits - 1ull;
-          const float4 e0 = e0s[i], e1 = e1s[i], e2 = e2s[i];
-          float dx, dy;
-          const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+          const float4 e0 = n0, e1 = n1, e2 = n2;
+          const uint32_t pos = base + (uint32_t)i;
+          i = c * kWave + (bits != 0ull ? __builtin_ctzll(bits) : 0);
+          n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i];
+          const float q = quad2(e0, e1.x, px[k], py[k]);
           const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
           const float a = fminf(amax, e1.y * G);
           const bool ok = have && (a >= amin);
@@ -234,7 +266,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
           C2[k] = fmaf(e2.z, wgt, C2[k]);
           D[k] = fmaf(e1.z, wgt, D[k]);
           T[k] = take ? Tn : T[k];
-          last[k] = take ? base + (uint32_t)i : last[k];
+          last[k] = take ? pos : last[k];
         }
       }
       if (wave_done()) break;
@@ -496,17 +528,22 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       unsigned long long own[PPT];
 #pragma unroll
       for (int k = 0; k < PPT; k++) own[k] = 0ull;
-      while (m) {
-        const int j = __builtin_ctzll(m);
+      while (m) {  // two entries per step, both loads issued first
+        const int ja = __builtin_ctzll(m);
         m &= m - 1;
-        const float4 e0 = e0s[c * kWave + j];
-        const float qc = e1s[c * kWave + j].x;
-        const int idx = lo + c * kWave + j - start;
+        const bool hb = m != 0ull;
+        const int jb = hb ? __builtin_ctzll(m) : ja;
+        m &= hb ? m - 1 : m;
+        const float4 a0 = e0s[c * kWave + ja], b0 = e0s[c * kWave + jb];
+        const float aq = e1s[c * kWave + ja].x, bq = e1s[c * kWave + jb].x;
+        const int ia = lo + c * kWave + ja - start, ib = lo + c * kWave + jb - start;
 #pragma unroll
         for (int k = 0; k < PPT; k++) {
           float dx, dy;
-          const float q = quad(e0, qc, px[k], py[k], dx, dy);
-          own[k] |= (idx < (int)last[k] && q <= qcut) ? (1ull << j) : 0ull;
+          const float qa = quad(a0, aq, px[k], py[k], dx, dy);
+          const float qb = quad(b0, bq, px[k], py[k], dx, dy);
+          own[k] |= (ia < (int)last[k] && qa <= qcut) ? (1ull << ja) : 0ull;
+          own[k] |= (ib < (int)last[k] && qb <= qcut) ? (1ull << jb) : 0ull;
         }
       }
       // 2. each lane replays its own entries, last to first
@@ -514,12 +551,17 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       for (int k = 0; k < PPT; k++) {
         unsigned long long bits = own[k];
         const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        // the next entry's LDS reads are issued before this one is replayed
+        int jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
+        float4 n0 = e0s[c * kWave + jj], n1 = e1s[c * kWave + jj], n2 = e2s[c * kWave + jj];
+        float4 nj = ejs[c * kWave + jj], np = eps_[c * kWave + jj];
         for (int n = 0; n < steps; n++) {
           const bool have = bits != 0ull;
-          const int jj = have ? 63 - __builtin_clzll(bits) : 0;
           bits &= have ? ~(1ull << jj) : ~0ull;
+          const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
+          jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
           const int i = c * kWave + jj;
-          const float4 e0 = e0s[i], e1 = e1s[i], e2 = e2s[i], ej = ejs[i], ep = eps_[i];
+          n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i]; nj = ejs[i]; np = eps_[i];
           float dx, dy;
           const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
           const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);

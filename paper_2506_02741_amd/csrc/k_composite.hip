@@ -405,10 +405,13 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.w, (float)ox, (float)oy);
       if (i >= nb) continue;
       const BwdEntry &E = st[k];
-      e0s[i] = E.e0; e1s[i] = E.e1; e2s[i] = E.e2;
+      // the twist walk stages the doubled off-diagonal conic term (exact)
+      // and keeps the plain one where the learnable flag would go
+      e0s[i] = kSlots ? E.e0 : make_float4(E.e0.x, E.e0.y, E.e0.z, 2.0f * E.e0.w);
+      e1s[i] = E.e1; e2s[i] = E.e2;
       const float iz = 1.0f / E.e1.z;
       ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * E.eb.x * iz * iz, -vfy * E.eb.y * iz * iz);
-      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, E.eb.z);
+      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, kSlots ? E.eb.z : E.e0.w);
       if (kSlots) {
         slot_s[i] = E.slot;
 #pragma unroll
@@ -525,27 +528,34 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       }
       if (m == 0ull) continue;
       // 1. which of the chunk's entries each of this lane's pixels composited
-      unsigned long long own[PPT];
+      uint32_t own_lo[PPT], own_hi[PPT];
 #pragma unroll
-      for (int k = 0; k < PPT; k++) own[k] = 0ull;
-      while (m) {  // two entries per step, both loads issued first
-        const int ja = __builtin_ctzll(m);
-        m &= m - 1;
-        const bool hb = m != 0ull;
-        const int jb = hb ? __builtin_ctzll(m) : ja;
-        m &= hb ? m - 1 : m;
-        const float4 a0 = e0s[c * kWave + ja], b0 = e0s[c * kWave + jb];
-        const float aq = e1s[c * kWave + ja].x, bq = e1s[c * kWave + jb].x;
-        const int ia = lo + c * kWave + ja - start, ib = lo + c * kWave + jb - start;
+      for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
+      for (int h = 0; h < 2; h++) {
+        uint32_t mh = (uint32_t)(m >> (32 * h));
+        while (mh) {  // two entries per step, both loads issued first
+          const int ja = __builtin_ctz(mh);
+          mh &= mh - 1u;
+          const bool hb = mh != 0u;
+          const int jb = hb ? __builtin_ctz(mh) : ja;
+          mh &= hb ? mh - 1u : mh;
+          const int sa = c * kWave + 32 * h + ja, sb = c * kWave + 32 * h + jb;
+          const float4 a0 = e0s[sa], b0 = e0s[sb];
+          const float aq = e1s[sa].x, bq = e1s[sb].x;
+          const int ia = lo + sa - start, ib = lo + sb - start;
 #pragma unroll
-        for (int k = 0; k < PPT; k++) {
-          float dx, dy;
-          const float qa = quad(a0, aq, px[k], py[k], dx, dy);
-          const float qb = quad(b0, bq, px[k], py[k], dx, dy);
-          own[k] |= (ia < (int)last[k] && qa <= qcut) ? (1ull << ja) : 0ull;
-          own[k] |= (ib < (int)last[k] && qb <= qcut) ? (1ull << jb) : 0ull;
+          for (int k = 0; k < PPT; k++) {
+            const float qa = quad2(a0, aq, px[k], py[k]);
+            const float qb = quad2(b0, bq, px[k], py[k]);
+            const uint32_t bits = ((ia < (int)last[k] && qa <= qcut) ? (1u << ja) : 0u) |
+                                  ((ib < (int)last[k] && qb <= qcut) ? (1u << jb) : 0u);
+            if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
+          }
         }
       }
+      unsigned long long own[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; k++) own[k] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
       // 2. each lane replays its own entries, last to first
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
@@ -562,8 +572,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
           const int i = c * kWave + jj;
           n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i]; nj = ejs[i]; np = eps_[i];
-          float dx, dy;
-          const float q = quad(e0, e1.x, px[k], py[k], dx, dy);
+          const float dx = px[k] - e0.x, dy = py[k] - e0.y;
+          const float q = quad2(e0, e1.x, px[k], py[k]);
           const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
           const float a = fminf(amax, e1.y * G);
           const bool ok = have && (a >= amin);
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           BS[k] = ok ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
           const bool pass = oG <= amax;
           const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
-          const float qb = e0.w;
+          const float qb = ep.w;
           const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
           const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
           const float kk = ep.z;

@@ -71,32 +71,42 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
   x0 = rc.x & 0xffff; y0 = rc.x >> 16; x1 = rc.y & 0xffff; y1 = rc.y >> 16;
 }
 
-// Visit every tile covered by the active lanes' rectangles.  When the whole
-// wave belongs to one view and its rectangles fit in a small bounding box,
-// each tile is handled once per wave: `f(tile, mask)` runs on every lane
-// with the ballot of lanes covering that tile (same value in all lanes).
-// Otherwise each lane visits its own tiles with mask = its own bit.
-template <typename F>
-__device__ __forceinline__ void for_tiles(bool has, int view, int x0, int y0, int x1, int y1,
-                                          int tiles_x, F &&f) {
+// Tiles covered by a wave's rectangles.  When the whole wave belongs to one
+// view and its rectangles fit in a bounding box of at most 24 tiles, tile j
+// of that box (row-major) is owned by lane j: `own(j, t, count)` runs once
+// on every lane with the owner's tile and the number of lanes covering it
+// (count 0: no lane covers tile j), so one instruction can issue an atomic
+// per tile from all owners at once; `visit(j, t, m, in)` then runs for each
+// box tile on every lane with the ballot m of lanes covering it.  Otherwise
+// (mixed views or a large box) each lane visits its own tiles alone through
+// `single(t)`.
+struct WaveBox {
+  int bx0, by0, nx, area;
+  bool shared;
+};
+
+__device__ __forceinline__ WaveBox wave_box(bool has, int view, int x0, int y0, int x1, int y1) {
+  WaveBox b;
   const int vmin = wave_min_i(has ? view : 0x7fffffff);
   const int vmax = wave_max_i(has ? view : -1);
-  if (vmax < 0) return;
-  const int bx0 = wave_min_i(has ? x0 : 0x7fffffff), by0 = wave_min_i(has ? y0 : 0x7fffffff);
+  b.bx0 = wave_min_i(has ? x0 : 0x7fffffff);
+  b.by0 = wave_min_i(has ? y0 : 0x7fffffff);
   const int bx1 = wave_max_i(has ? x1 : -1), by1 = wave_max_i(has ? y1 : -1);
-  const long area = (long)(bx1 - bx0 + 1) * (long)(by1 - by0 + 1);
-  if (vmin == vmax && area <= 24) {
-    for (int ty = by0; ty <= by1; ty++)
-      for (int tx = bx0; tx <= bx1; tx++) {
-        const bool in = has && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
-        const unsigned long long m = ballot64(in);
-        if (m) f(ty * tiles_x + tx, m, in);
-      }
-  } else if (has) {
-    const unsigned long long me = 1ull << lane_id();
-    for (int ty = y0; ty <= y1; ty++)
-      for (int tx = x0; tx <= x1; tx++) f(ty * tiles_x + tx, me, true);
-  }
+  b.nx = bx1 - b.bx0 + 1;
+  const long area = vmax < 0 ? 0 : (long)b.nx * (long)(by1 - b.by0 + 1);
+  b.shared = vmax >= 0 && vmin == vmax && area <= 24;
+  b.area = b.shared ? (int)area : 0;
+  return b;
+}
+
+// ballot of the lanes whose rectangle covers box tile j
+__device__ __forceinline__ unsigned long long box_ballot(const WaveBox &b, int j, bool has, int x0,
+                                                        int y0, int x1, int y1, int &tx, int &ty,
+                                                        bool &in) {
+  ty = b.by0 + j / b.nx;
+  tx = b.bx0 + j % b.nx;
+  in = has && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
+  return ballot64(in);
 }
 
 __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
@@ -166,10 +176,22 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
   }
   uint32_t *cnt = ws.tile_count + tile_base;
-  for_tiles(has, view, x0, y0, x1, y1, tiles_x,
-            [&](int t, unsigned long long m, bool in) {
-              if (lane_id() == __ffsll((long long)m) - 1) atomicAdd(cnt + t, (uint32_t)__popcll(m));
-            });
+  const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
+  if (box.shared) {
+    // lane j counts box tile j; one atomic instruction for the whole box
+    uint32_t mine = 0u;
+    int mt = 0;
+    for (int j = 0; j < box.area; j++) {
+      int tx, ty;
+      bool in;
+      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
+      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = ty * tiles_x + tx; }
+    }
+    if (mine) atomicAdd(cnt + mt, mine);
+  } else if (has) {
+    for (int ty = y0; ty <= y1; ty++)
+      for (int tx = x0; tx <= x1; tx++) atomicAdd(cnt + ty * tiles_x + tx, 1u);
+  }
 }
 
 // One block: tile counts -> ranges (clamped to the pair capacity), total
@@ -228,20 +250,43 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     const float z = ws.recA[3 * (int64_t)r + 1].z;
     key = ((unsigned long long)__float_as_uint(z) << 32) | (uint32_t)(r - vw.rec_base);
   }
-  for_tiles(has, view, x0, y0, x1, y1, tiles_x,
-            [&](int t, unsigned long long m, bool in) {
-              const int leader = __ffsll((long long)m) - 1;
-              uint32_t base = 0;
-              if (lane_id() == leader) {
-                const uint32_t slot = atomicAdd(ws.tile_fill + tile_base + t, (uint32_t)__popcll(m));
-                base = ws.ranges[tile_base + t].x + slot;
-              }
-              base = (uint32_t)__shfl((int)base, leader);
-              if (in) {
-                const uint32_t pos = base + (uint32_t)__popcll(m & lanemask_lt());
-                if (pos < ws.ranges[tile_base + t].y) ws.keys[pos] = key;
-              }
-            });
+  const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
+  if (box.shared) {
+    // lane j claims the wave's slots in box tile j (all tiles in one round
+    // trip), then every tile's base is read from its owner lane
+    uint32_t mine = 0u;
+    int mt = 0;
+    for (int j = 0; j < box.area; j++) {
+      int tx, ty;
+      bool in;
+      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
+      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = tile_base + ty * tiles_x + tx; }
+    }
+    uint32_t base = 0u, lim = 0u;
+    if (mine) {
+      const uint2 rg = ws.ranges[mt];
+      base = rg.x + atomicAdd(ws.tile_fill + mt, mine);
+      lim = rg.y;
+    }
+    for (int j = 0; j < box.area; j++) {
+      int tx, ty;
+      bool in;
+      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
+      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base, j);
+      const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)lim, j);
+      if (in) {
+        const uint32_t pos = b + (uint32_t)__popcll(m & lanemask_lt());
+        if (pos < e) ws.keys[pos] = key;
+      }
+    }
+  } else if (has) {
+    for (int ty = y0; ty <= y1; ty++)
+      for (int tx = x0; tx <= x1; tx++) {
+        const int t = tile_base + ty * tiles_x + tx;
+        const uint32_t pos = ws.ranges[t].x + atomicAdd(ws.tile_fill + t, 1u);
+        if (pos < ws.ranges[t].y) ws.keys[pos] = key;
+      }
+  }
 }
 
 constexpr int kSortCap = 8192;

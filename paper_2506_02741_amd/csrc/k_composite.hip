@@ -31,10 +31,11 @@
 //   k = 2 r^2 / p_z.
 // Mode "twist": dL/dp is chained straight to the view's left twist
 // (rho += dL/dp, phi += p x dL/dp) in registers, summed per tile.
-// Mode "slots": (dL/dc, dL/do, dL/dr) are summed over the wave, then over
-// the four waves, and written to the pair's (record, tile) slot; a gather
-// pass sums a record's slots.  Neither mode uses global atomics, so both
-// are deterministic.
+// Mode "slots": each lane adds its (dL/dc, dL/do, dL/dr) for an entry into
+// its wave's own LDS accumulators (LDS atomics, in the wave's program
+// order); after a batch the four waves' sums go to the pair's (record, tile)
+// slot, and a gather pass sums a record's slots.  Neither mode uses global
+// atomics and no two waves share an accumulator, so both are deterministic.
 #include "vtgs_internal.h"
 
 namespace vtgs {
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   constexpr int NCH = PER * NT / kWave;
   constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
   constexpr int AB = kSlots ? BATCH : 1;
+  // staged entry: e0 (mx, my, qa, 2 qb), e1 (qc, o, z, qb), e2 (c, r)
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
   __shared__ float4 ejs[BATCH];   // (fx/z, fy/z, -fx px/z^2, -fy py/z^2)
   __shared__ float4 eps_[BATCH];  // (px, py, 2 r^2 / z, learnable)
@@ -405,13 +407,14 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.w, (float)ox, (float)oy);
       if (i >= nb) continue;
       const BwdEntry &E = st[k];
-      // the twist walk stages the doubled off-diagonal conic term (exact)
-      // and keeps the plain one where the learnable flag would go
-      e0s[i] = kSlots ? E.e0 : make_float4(E.e0.x, E.e0.y, E.e0.z, 2.0f * E.e0.w);
-      e1s[i] = E.e1; e2s[i] = E.e2;
+      // the doubled off-diagonal conic term (exact) for q, the plain one
+      // (in place of the extent, which staging no longer needs) for dq
+      e0s[i] = make_float4(E.e0.x, E.e0.y, E.e0.z, 2.0f * E.e0.w);
+      e1s[i] = make_float4(E.e1.x, E.e1.y, E.e1.z, E.e0.w);
+      e2s[i] = E.e2;
       const float iz = 1.0f / E.e1.z;
       ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * E.eb.x * iz * iz, -vfy * E.eb.y * iz * iz);
-      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, kSlots ? E.eb.z : E.e0.w);
+      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, E.eb.z);
       if (kSlots) {
         slot_s[i] = E.slot;
 #pragma unroll
@@ -429,103 +432,12 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
         if (i < BATCH && nlo + i < lo) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
       }
     }
-    // one staged entry (batch position j) against this lane's pixels
-    auto step = [&](int j) {
-      const float4 e0 = e0s[j], e1 = e1s[j], e2 = e2s[j], ej = ejs[j], ep = eps_[j];
-      const int idx = lo + j - start;
-      bool ok[PPT];
-      float dxs[PPT], dys[PPT], qs[PPT], Gs[PPT], as[PPT];
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        qs[k] = quad(e0, e1.x, px[k], py[k], dxs[k], dys[k]);
-        ok[k] = (idx < (int)last[k]) && (qs[k] <= qcut);
-        any = any || ok[k];
-      }
-      if (ballot64(any) == 0ull) return;
-#pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        Gs[k] = __builtin_amdgcn_exp2f(qs[k] * kNegHalfLog2e);
-        as[k] = fminf(amax, e1.y * Gs[k]);
-        ok[k] = ok[k] && (as[k] >= amin);
-      }
-      float sc0 = 0.f, sc1 = 0.f, sc2 = 0.f, so = 0.f, sr = 0.f;
-#pragma unroll
-      for (int k = 0; k < PPT; k++) {
-        const float a = as[k], G = Gs[k], oG = e1.y * G;
-        const float om = 1.0f - a;
-        const float Tk = ok[k] ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
-        T[k] = Tk;
-        const float wgt = ok[k] ? a * Tk : 0.f;
-        float dLda = gC0[k] * (e2.x - BC0[k]);
-        dLda = fmaf(gC1[k], e2.y - BC1[k], dLda);
-        dLda = fmaf(gC2[k], e2.z - BC2[k], dLda);
-        dLda = fmaf(gD[k], e1.z - BD[k], dLda);
-        dLda = fmaf(gS[k], 1.0f - BS[k], dLda);
-        dLda = ok[k] ? dLda * Tk : 0.f;
-        BC0[k] = ok[k] ? fmaf(a, e2.x, om * BC0[k]) : BC0[k];
-        BC1[k] = ok[k] ? fmaf(a, e2.y, om * BC1[k]) : BC1[k];
-        BC2[k] = ok[k] ? fmaf(a, e2.z, om * BC2[k]) : BC2[k];
-        BD[k] = ok[k] ? fmaf(a, e1.z, om * BD[k]) : BD[k];
-        BS[k] = ok[k] ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
-        const bool pass = oG <= amax;
-        const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
-        // t = J^T Q d
-        const float dx = dxs[k], dy = dys[k];
-        const float qb = e0.w;
-        const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
-        const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
-        if (kTwist) {
-          const float kk = ep.z;
-          const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
-          const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
-          const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
-          const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
-          const float pz = e1.z;
-          tw[0] += g0; tw[1] += g1; tw[2] += g2;
-          tw[3] += ep.y * g2 - pz * g1;
-          tw[4] += pz * g0 - ep.x * g2;
-          tw[5] += ep.x * g1 - ep.y * g0;
-        }
-        if (kSlots) {
-          sc0 = fmaf(wgt, gC0[k], sc0);
-          sc1 = fmaf(wgt, gC1[k], sc1);
-          sc2 = fmaf(wgt, gC2[k], sc2);
-          so = pass ? fmaf(G, dLda, so) : so;
-          const float tt = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
-          sr = fmaf(dLdq, -2.0f * e2.w * tt, sr);
-        }
-      }
-      if (kSlots && ep.w != 0.f) {
-        float rt, r4;
-        wave_sum5(sc0, sc1, sc2, so, sr, rt, r4);
-        const int l = lane_id();
-        if ((l & 15) == 0) {
-          const int row = l >> 4;  // rows hold the sums of (c0, c2, c1, opacity)
-          acc[w][row == 1 ? 2 : row == 2 ? 1 : row][j] = rt;
-          if (row == 0) acc[w][4][j] = r4;
-        }
-      }
-    };
     // this wave's entries, last to first, below its own last contributor
     const int lim = min(nb, wstop - lo);
     for (int c = (lim - 1) / kWave; lim > 0 && c >= 0; c--) {
       unsigned long long m = uniform_u64(masks[w][c]);
       const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
       if (top < kWave) m &= (1ull << top) - 1ull;
-      if (kSlots) {
-        // slot sums need every lane on the same entry
-        while (m) {
-          const int ja = 63 - __builtin_clzll(m);
-          m &= ~(1ull << ja);
-          step(c * kWave + ja);
-          if (!m) break;
-          const int jb = 63 - __builtin_clzll(m);
-          m &= ~(1ull << jb);
-          step(c * kWave + jb);
-        }
-        continue;
-      }
       if (m == 0ull) continue;
       // 1. which of the chunk's entries each of this lane's pixels composited
       uint32_t own_lo[PPT], own_hi[PPT];
@@ -569,9 +481,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const bool have = bits != 0ull;
           bits &= have ? ~(1ull << jj) : ~0ull;
           const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
+          const int cur = c * kWave + jj;  // this entry's batch position
           jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
-          const int i = c * kWave + jj;
-          n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i]; nj = ejs[i]; np = eps_[i];
+          const int nxt = c * kWave + jj;
+          n0 = e0s[nxt]; n1 = e1s[nxt]; n2 = e2s[nxt]; nj = ejs[nxt]; np = eps_[nxt];
           const float dx = px[k] - e0.x, dy = py[k] - e0.y;
           const float q = quad2(e0, e1.x, px[k], py[k]);
           const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
@@ -595,19 +508,30 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           BS[k] = ok ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
           const bool pass = oG <= amax;
           const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
-          const float qb = ep.w;
+          const float qb = e1.w;
           const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
           const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
-          const float kk = ep.z;
-          const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
-          const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
-          const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
-          const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
-          const float pz = e1.z;
-          tw[0] += g0; tw[1] += g1; tw[2] += g2;
-          tw[3] += ep.y * g2 - pz * g1;
-          tw[4] += pz * g0 - ep.x * g2;
-          tw[5] += ep.x * g1 - ep.y * g0;
+          if (kTwist) {
+            const float kk = ep.z;
+            const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
+            const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
+            const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
+            const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+            const float pz = e1.z;
+            tw[0] += g0; tw[1] += g1; tw[2] += g2;
+            tw[3] += ep.y * g2 - pz * g1;
+            tw[4] += pz * g0 - ep.x * g2;
+            tw[5] += ep.x * g1 - ep.y * g0;
+          }
+          if (kSlots && ok && ep.w != 0.f) {
+            // this wave's accumulators: only its own lanes add to them
+            const float tt = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
+            atomicAdd(&acc[w][0][cur], wgt * gC0[k]);
+            atomicAdd(&acc[w][1][cur], wgt * gC1[k]);
+            atomicAdd(&acc[w][2][cur], wgt * gC2[k]);
+            atomicAdd(&acc[w][3][cur], pass ? G * dLda : 0.f);
+            atomicAdd(&acc[w][4][cur], dLdq * (-2.0f * e2.w * tt));
+          }
         }
       }
     }

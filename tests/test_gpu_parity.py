@@ -314,22 +314,31 @@ def test_uneven_resolutions_batch(R, orc):
 # determinism, capacity, edge cases
 # ----------------------------------------------------------------------------
 
-def test_deterministic(R):
-    cam, frames, vpose = room_frames(5, 80, 60)
-    k = gpu_kf(R, frames[0], learnable=True).with_grad_buffers()
-    plan = R.Plan([k], [R.View(cam.as_tuple(), vpose)])
+@pytest.mark.parametrize("n_kf", [1, 3])
+def test_deterministic(R, n_kf):
+    """Repeated passes give bit-identical images, twists and per-Gaussian
+    gradients (the gradient sums run in a fixed order)."""
+    cam, frames, vpose = room_frames(5 if n_kf == 1 else 9, 80, 60, n_kf=n_kf)
+    ks = [gpu_kf(R, f, learnable=True).with_grad_buffers() for f in frames]
+    plan = R.Plan(ks, [R.View(cam.as_tuple(), vpose, 0, n_kf)])
     rng = np.random.default_rng(2)
     g = T(rng.normal(size=(3, plan.P)))
+    gd = T(rng.normal(size=plan.P))
     out = []
-    for _ in range(2):
-        k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+    for _ in range(4):
+        for k in ks:
+            k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
         imgs = [np_(x) for x in plan.render_fwd()]
-        tw = np_(plan.render_bwd(g, None, None))
-        out.append((imgs, tw, np_(k.g_color), np_(k.g_radius)))
-    for a, b in zip(out[0][0], out[1][0]):
-        assert np.array_equal(a, b)
-    for i in (1, 2, 3):
-        assert np.array_equal(out[0][i], out[1][i])
+        tw = np_(plan.render_bwd(g, gd, None))
+        out.append((imgs, tw, [np_(k.g_color) for k in ks], [np_(k.g_opacity) for k in ks],
+                    [np_(k.g_radius) for k in ks]))
+    for o in out[1:]:
+        for a, b in zip(out[0][0], o[0]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(out[0][1], o[1])
+        for i in (2, 3, 4):
+            for a, b in zip(out[0][i], o[i]):
+                assert np.array_equal(a, b)
 
 
 def test_capacity_overflow_is_reported_and_recoverable(R, orc):

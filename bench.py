@@ -61,14 +61,46 @@ def run_frames(plan, view, init, cfg, iters, loss):
 
 
 def flops_per_pair():
-    """FP32 operations the definition needs per (pixel, Gaussian) pair of the
-    backward compositing (twist chain) and the forward compositing:
-    a tested pair evaluates d and q (8); a covering pair (q <= q_cut) adds
-    exp and alpha (4); a contributing pair adds, forward, the transmittance
-    and colour/depth accumulation (11), backward, transmittance recovery,
-    dL/dalpha, the behind accumulators and dL/dq (27) and the chain to the
-    twist (34)."""
-    return dict(fwd_test=8, fwd_cover=4, fwd_contrib=11, bwd_test=8, bwd_cover=4, bwd_contrib=61)
+    """FP32 operations per contributing (pixel, Gaussian) pair, counted from
+    the compositing arithmetic (add, mul, min = 1; fma = 2; exp2, rcp = 1;
+    compares and selects not counted).  Forward: d (2), q (8), G (2), alpha
+    (2), transmittance (2), weight (1), colour and depth accumulation (8) =
+    25.  Backward to the twist: d and q (10), G (2), alpha (2), o G and
+    1 - alpha (2), T recovery (2), weight (1), dL/dalpha (15), the behind
+    accumulators (15), dL/dq (2), w = Q d and t = J^T w (11), dL/dp (16),
+    rho and phi sums (15) = 99.  Pairs that cover a pixel without
+    contributing are not counted (a lower bound on the work)."""
+    return dict(fwd_contrib=25, bwd_contrib=99)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_bwd_tracking_640x480_traffic.txt")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2506_02741_amd", "csrc", f)
+                   for f in ("k_composite.hip", "vtgs_internal.h")]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the tracking backward from the committed
+    counter summary, or None when the kernel sources changed since the
+    counters were taken (the summary records their SHA-256)."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    if kv.get("sources_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pair_counts(w):
@@ -306,19 +338,18 @@ def main():
     contrib, _ = pair_counts(w)
     fl = flops_per_pair()
     roof = None
-    if dom == "composite_bwd":
-        work = contrib * fl["bwd_contrib"]
-    elif dom == "composite_fwd":
-        work = contrib * fl["fwd_contrib"]
-    else:
-        work = None
-    if work is not None:
+    per = {"composite_bwd": fl["bwd_contrib"], "composite_fwd": fl["fwd_contrib"]}.get(dom)
+    if per is not None:
+        work = contrib * per
         achieved = work / (avg[dom] * 1e-3) / 1e12
         roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS, traffic=None,
+                    unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS,
+                    traffic=measured_traffic() if dom == "composite_bwd" else None,
                     avg_ms=avg[dom], flops_per_launch=work,
-                    units="%d contributing (pixel, Gaussian) pairs x %d FLOP" % (
-                        contrib, fl["bwd_contrib"] if dom == "composite_bwd" else fl["fwd_contrib"]))
+                    units="%d contributing (pixel, Gaussian) pairs x %d FLOP" % (contrib, per))
+        fw = avg.get("composite_fwd")
+        if fw:
+            roof["composite_fwd"] = dict(avg_ms=fw, achieved=contrib * fl["fwd_contrib"] / (fw * 1e-3) / 1e12)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -336,7 +367,8 @@ def main():
         serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_sections,
                               args.serve_budget_gib)
 
-    out = dict(metric="fwd+bwd Mpix/s at 640x480", value=value, unit="Mpix/s", n_gpus=1,
+    out = dict(metric="fwd+bwd Mpix/s at 640x480 vs 1-view/launch; p50/p99 render-request latency",
+               value=value, unit="Mpix/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic",

@@ -120,3 +120,33 @@ def test_unbound_plan_and_null_args(L):
     assert L.vtgs_ingest_count(None, None, 4, 4, 1, None, 0, None, None) == _lib.VTGS_E_ARG
     assert L.vtgs_ingest_scratch_bytes(480, 640, 1) > 0
     assert L.vtgs_ingest_scratch_bytes(0, 640, 1) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_summary_tracks_kernel_sources(tmp_path, monkeypatch):
+    """The committed counter summary is used only while the kernel sources
+    still hash to the value it records."""
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    src = tmp_path / "k.hip"
+    src.write_bytes(b"kernel source")
+    import hashlib
+    good = hashlib.sha256(b"kernel source").hexdigest()
+    f = tmp_path / "traffic.txt"
+    f.write_text("hbm_bytes_per_launch: 1234\nsources_sha256: %s\n" % good)
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(b, "TRAFFIC_SOURCES", [str(src)])
+    assert b.measured_traffic() == 1234.0
+    src.write_bytes(b"kernel source, changed")
+    assert b.measured_traffic() is None

@@ -199,6 +199,80 @@ def batched_vs_single(iters):
                 speedup=ts / tb, batched_stages_ms=bstages, pairs=pairs)
 
 
+def uneven_run(reps):
+    """16 views of mixed resolution (320x240 / 640x480 / 1200x680) drawn from a
+    3-section map of 24 keyframes; each view renders its section (8
+    keyframes) and back-propagates to colour/opacity/radius.  The tile/batch
+    shape comes from the autotuner's sweep; the batch runs as one captured
+    graph of forward + backward, against one view per launch."""
+    import tempfile
+    import numpy as np
+    import torch
+    from paper_2506_02741_amd import autotune
+    from paper_2506_02741_amd import render as R
+    from paper_2506_02741_amd import synth
+    t0 = time.perf_counter()
+    w = synth.uneven_workload(3)
+    frames = [f for sec in w["sections"] for f in sec]
+    gen_s = time.perf_counter() - t0
+    ks = [R.Keyframe.ingest(f.depth, f.rgb, f.cam.as_tuple(), f.pose, learnable=True).with_grad_buffers()
+          for f in frames]
+    views = [R.View(frames[v].cam.as_tuple(), frames[v].pose, 8 * (v // 8), 8) for v in w["views"]]
+    px = sum(v.cam.width * v.cam.height for v in views)
+    os.environ["VTGS_AUTOTUNE_CACHE"] = os.path.join(tempfile.mkdtemp(), "autotune.json")
+    prm, entry = autotune.tune(ks, views, mode="map", reps=3, force=True)
+
+    def timed_graph(prm):
+        plan, _ = R.plan_checked(ks, views, prm, run=lambda p: (
+            p.render_fwd(), p.render_bwd(gw(p), None, None, twist=False)))
+        g = gw(plan)
+        plan.render_fwd(); plan.render_bwd(g, None, None, twist=False)
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            plan.render_fwd()
+            plan.render_bwd(g, None, None, twist=False)
+        graph.replay()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        assert plan.status()[0] == 0
+        return dt, plan.cap
+
+    def gw(plan):
+        return torch.ones(3, plan.P, device="cuda") * 1e-3
+    tuned_s, cap = timed_graph(prm)
+    default_s, _ = timed_graph(R.params())
+    # one view per launch: forward, host sync sizing the pair list, backward
+    singles = [R.plan_checked(ks, [v], prm, run=lambda p: (
+        p.render_fwd(), p.render_bwd(gw(p), None, None, twist=False)))[0] for v in views]
+    gs = [gw(p) for p in singles]
+    for p, g in zip(singles, gs):
+        p.render_fwd(); p.render_bwd(g, None, None, twist=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(max(1, reps // 2)):
+        for p, g in zip(singles, gs):
+            p.render_fwd()
+            p.status(clear=False)
+            p.render_bwd(g, None, None, twist=False)
+    torch.cuda.synchronize()
+    single_s = (time.perf_counter() - t) / max(1, reps // 2)
+    n_gauss = sum(k.n for k in ks)
+    return dict(workload="16 views (320x240/640x480/1200x680 uniform) of a 3-section map of 24 "
+                         "keyframes, each view over its 8-keyframe section, fwd+bwd to "
+                         "colour/opacity/radius, one captured graph",
+                map_gaussians=n_gauss, pixels=px, tuned=dict(tile=entry["tile"], batch=entry["batch"]),
+                sweep_ms=entry["sweep"], graph_mpix_s=px / tuned_s / 1e6,
+                default_shape_mpix_s=px / default_s / 1e6, one_view_per_launch_mpix_s=px / single_s / 1e6,
+                speedup=single_s / tuned_s, generation_s=gen_s)
+
+
 def serving_run(seconds, rate, n_sections, budget_gib, seed=4):
     """Poisson render/track requests against a device-resident map of
     n_sections x 10 keyframes at 1200x680, stride 2.  The map is built from
@@ -271,6 +345,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--uneven-reps", type=int, default=6)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes 256 MiB (known "
                          "traffic for scaling hardware byte counters)")
@@ -361,6 +437,11 @@ def main():
         log("bench: batched vs one view per launch")
         batched = batched_vs_single(args.batched_iters)
 
+    uneven = None
+    if not args.no_uneven:
+        log("bench: uneven 16-view batch with autotuned tiles")
+        uneven = uneven_run(args.uneven_reps)
+
     serving = None
     if not args.no_serving:
         log("bench: serving %g s at %g req/s" % (args.serve_seconds, args.serve_rate))
@@ -375,7 +456,8 @@ def main():
                config=dict(workload="tracking 640x480: 1 keyframe, 307,200 view-tied Gaussians, "
                                     "40-iteration frames of fwd + Eq.1 + bwd to twist + pose step",
                            global_batch=1, seq_len=0, parallelism="none"),
-               roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched, serving=serving)
+               roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched, uneven=uneven,
+               serving=serving)
     print(json.dumps(out), flush=True)
 
 

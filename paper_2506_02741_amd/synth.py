@@ -166,13 +166,20 @@ def make_room(seed: int, n_boxes=10, n_spheres=10, size=(5.0, 4.0, 3.0)) -> Scen
     return Scene(lo, hi, boxes, spheres, [], _surface_params(rng, n_surf))
 
 
+def _rows_times(x, M):
+    """x[n,3] @ M[3,3] as explicit sums in a fixed order (no BLAS, so the
+    result does not depend on library threading)."""
+    return np.stack([(x[:, 0] * M[0, j] + x[:, 1] * M[1, j]) + x[:, 2] * M[2, j] for j in range(3)],
+                    axis=1)
+
+
 def ray_cast(scene: Scene, cam: Camera, pose_w2c, with_color=True):
     """Return (depth[H,W] float32 z-depth, rgb[3,H,W] float32 or None, hit_pts)."""
     W, H = cam.width, cam.height
     R_c2w, c = c2w_from_w2c(pose_w2c)
     u, v = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
     d_cam = np.stack([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, np.ones_like(u)], -1)
-    d = d_cam.reshape(-1, 3) @ R_c2w.T           # world direction with z-component 1 in camera
+    d = _rows_times(d_cam.reshape(-1, 3), R_c2w.T)  # world direction, camera-z component 1
     o = np.broadcast_to(c, d.shape)
     n = d.shape[0]
     t_best = np.full(n, np.inf)
@@ -193,8 +200,8 @@ def ray_cast(scene: Scene, cam: Camera, pose_w2c, with_color=True):
         base = 6
         for bi, (bc, half, yaw) in enumerate(scene.boxes):
             Rb = axis_angle((0, 0, 1), yaw)
-            ol = (o - bc) @ Rb
-            dl = d @ Rb
+            ol = _rows_times(o - bc, Rb)
+            dl = _rows_times(d, Rb)
             t1 = (-half - ol) / dl
             t2 = (half - ol) / dl
             tmin = np.max(np.minimum(t1, t2), axis=1)
@@ -309,6 +316,14 @@ def frame(scene, cam, pose) -> Frame:
     return Frame(cam, np.asarray(pose, np.float32), d, rgb)
 
 
+def _frames(scene, jobs, workers=8):
+    """frame() over (camera, pose) pairs on a thread pool (same arrays as a
+    sequential loop: the ray caster has no BLAS products)."""
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(lambda a: frame(scene, a[0], a[1]), jobs))
+
+
 def toy_scene(seed=0, width=64, height=48, f=60.0, n_spheres=3):
     """Toy single view: back plane at 3.5 m plus spheres at 1-2.5 m whose
     projected centres lie in the central 60% of the image; identity pose.
@@ -325,8 +340,8 @@ def toy_scene(seed=0, width=64, height=48, f=60.0, n_spheres=3):
         pv = rng.uniform(0.2 * height, 0.8 * height)
         c = np.array([(pu - cam.cx) / cam.fx * z, (pv - cam.cy) / cam.fy * z, z])
         a = np.sum(d * d, 1)
-        b = -2 * d @ c
-        cc = c @ c - rad * rad
+        b = -2 * ((d[:, 0] * c[0] + d[:, 1] * c[1]) + d[:, 2] * c[2])
+        cc = (c[0] * c[0] + c[1] * c[1]) + c[2] * c[2] - rad * rad
         disc = b * b - 4 * a * cc
         t = (-b - np.sqrt(np.maximum(disc, 0))) / (2 * a)
         ok = (disc >= 0) & (t > 0) & (t < t_best)
@@ -356,7 +371,7 @@ def section_workload(seed=2, n_kf=8, width=640, height=480):
     scene = make_room(seed)
     cam = camera_for(width, height)
     poses = random_walk(scene, cam, rng, n_kf)
-    return dict(scene=scene, keyframes=[frame(scene, cam, T) for T in poses])
+    return dict(scene=scene, keyframes=_frames(scene, [(cam, T) for T in poses]))
 
 
 def draw_views(seed, n_total, n_pick, iters):
@@ -368,16 +383,18 @@ def draw_views(seed, n_total, n_pick, iters):
 RESOLUTIONS = ((320, 240), (640, 480), (1200, 680))
 
 
-def uneven_workload(seed=3, n_sections=3, kf_per_section=8, n_views=16):
+def uneven_workload(seed=3, n_sections=3, kf_per_section=8, n_views=16, workers=8):
     """Sections of keyframes whose resolutions are drawn uniformly from
-    320x240 / 640x480 / 1200x680, and views drawn from the keyframes."""
+    320x240 / 640x480 / 1200x680, and views drawn from the keyframes.  The
+    frames are ray-cast on `workers` threads (same arrays for any count)."""
     rng = np.random.default_rng(seed)
     scene = make_room(seed)
-    sections = []
+    jobs = []
     for _ in range(n_sections):
         res = [RESOLUTIONS[i] for i in rng.integers(0, 3, size=kf_per_section)]
         poses = random_walk(scene, camera_for(320, 240), rng, kf_per_section)
-        sections.append([frame(scene, camera_for(*wh), T) for wh, T in zip(res, poses)])
+        jobs.append(list(zip(res, poses)))
+    sections = [_frames(scene, [(camera_for(*wh), T) for wh, T in sec], workers) for sec in jobs]
     views = [int(x) for x in rng.integers(0, n_sections * kf_per_section, size=n_views)]
     return dict(scene=scene, sections=sections, views=views)
 
@@ -404,8 +421,9 @@ def serving_sections(seed=4, n_unique=3, kf_per_section=10, width=1200, height=6
     cam = camera_for(width, height)
     sub = Camera(cam.fx / stride, cam.fy / stride, cam.cx / stride, cam.cy / stride,
                  width // stride, height // stride)
-    sections = []
-    for _ in range(n_unique):
-        poses = random_walk(scene, sub, rng, kf_per_section)
-        sections.append([strided_frame(scene, cam, T, stride) for T in poses])
+    walks = [random_walk(scene, sub, rng, kf_per_section) for _ in range(n_unique)]
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(8) as ex:
+        sections = [list(ex.map(lambda T: strided_frame(scene, cam, T, stride), poses))
+                    for poses in walks]
     return dict(scene=scene, sections=sections, cam=cam, stride=stride)

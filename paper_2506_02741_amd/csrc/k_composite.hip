@@ -19,9 +19,11 @@
 //
 // Backward replays the same list from the last contributor towards the
 // front, recovering T_i = T_{i+1} / (1 - alpha_i) and keeping the colour,
-// depth and coverage of everything behind i, B <- alpha x + (1 - alpha) B.
-// Per contributing pair:
-//   dL/dalpha = T [g_C.(c - B_C) + g_D (z - B_D) + g_S (1 - B_S)]
+// depth and coverage of everything behind i, B <- alpha x + (1 - alpha) B
+// with x = (c, z, 1).  Only g . B enters the gradient, so one scalar per
+// pixel is carried: S <- alpha (g . x) + (1 - alpha) S, S = g_C . bg at the
+// back.  Per contributing pair:
+//   dL/dalpha = T [g_C.(c - B_C) + g_D (z - B_D) + g_S (1 - B_S)] = T (g . x - S)
 //   dL/dc = alpha T g_C, dL/dz = alpha T g_D,
 //   if o G <= alpha_max: dL/do = G dL/dalpha, dL/dq = -o G dL/dalpha / 2
 // and q's dependence on the camera-frame centre p and the radius r
@@ -353,7 +355,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   const int w = threadIdx.x / kWave;
 
   float px[PPT], py[PPT], T[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gS[PPT];
-  float BC0[PPT], BC1[PPT], BC2[PPT], BD[PPT], BS[PPT];
+  // g . B: the upstream gradient against what lies behind (colour, depth,
+  // coverage), one scalar per pixel
+  float SB[PPT];
   uint32_t last[PPT];
   uint32_t mylast = 0;
 #pragma unroll
@@ -371,8 +375,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
     gC2[k] = (valid && g_rgb) ? g_rgb[2 * P + p] : 0.f;
     gD[k] = (valid && g_depth) ? g_depth[p] : 0.f;
     gS[k] = (valid && g_sil) ? g_sil[p] : 0.f;
-    BC0[k] = ws.bg[0]; BC1[k] = ws.bg[1]; BC2[k] = ws.bg[2];
-    BD[k] = 0.f; BS[k] = 0.f;
+    SB[k] = fmaf(gC0[k], ws.bg[0], fmaf(gC1[k], ws.bg[1], gC2[k] * ws.bg[2]));
     mylast = max(mylast, last[k]);
   }
   if (threadIdx.x == 0) maxlast_s = 0;
@@ -495,17 +498,11 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const float Tk = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
           T[k] = Tk;
           const float wgt = ok ? a * Tk : 0.f;
-          float dLda = gC0[k] * (e2.x - BC0[k]);
-          dLda = fmaf(gC1[k], e2.y - BC1[k], dLda);
-          dLda = fmaf(gC2[k], e2.z - BC2[k], dLda);
-          dLda = fmaf(gD[k], e1.z - BD[k], dLda);
-          dLda = fmaf(gS[k], 1.0f - BS[k], dLda);
-          dLda = ok ? dLda * Tk : 0.f;
-          BC0[k] = ok ? fmaf(a, e2.x, om * BC0[k]) : BC0[k];
-          BC1[k] = ok ? fmaf(a, e2.y, om * BC1[k]) : BC1[k];
-          BC2[k] = ok ? fmaf(a, e2.z, om * BC2[k]) : BC2[k];
-          BD[k] = ok ? fmaf(a, e1.z, om * BD[k]) : BD[k];
-          BS[k] = ok ? fmaf(a, 1.0f, om * BS[k]) : BS[k];
+          // g . x for this Gaussian: x = (colour, depth, 1)
+          const float gx = fmaf(gC0[k], e2.x, fmaf(gC1[k], e2.y, fmaf(gC2[k], e2.z,
+                                                                  fmaf(gD[k], e1.z, gS[k]))));
+          const float dLda = ok ? (gx - SB[k]) * Tk : 0.f;
+          SB[k] = ok ? fmaf(a, gx, om * SB[k]) : SB[k];
           const bool pass = oG <= amax;
           const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
           const float qb = e1.w;

@@ -88,8 +88,8 @@ struct vtgs_plan {
   bool any_learnable = false;
   // workspace layout
   Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
-      r_ranges, r_keys, r_keys_tmp, r_ids, r_slots, r_tfinal, r_last, r_img, r_gimg, r_twist,
-      r_loss, r_ssim_map, r_ssim_part;
+      r_ranges, r_keys, r_keys_tmp, r_ids, r_slots, r_bits, r_tfinal, r_last, r_img, r_gimg,
+      r_twist, r_loss, r_ssim_map, r_ssim_part;
   int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
   int64_t ws_bytes = 0;
   // binding
@@ -153,6 +153,9 @@ void layout(vtgs_plan *p) {
   take(p->r_keys_tmp, cap * 8);
   take(p->r_ids, cap * 4);
   take(p->r_slots, p->any_learnable ? cap * 20 : 0);
+  // per 64-entry chunk of a tile list: each lane's bit mask of the entries
+  // that reach its pixel(s), written by the forward, read by the backward
+  take(p->r_bits, (cap / 64 + nt + 2) * (int64_t)lane_bits_per_chunk(p->prm.tile) * 8);
   take(p->r_tfinal, P * 4);
   take(p->r_last, P * 4);
   take(p->r_img, 5 * P * 4);
@@ -201,6 +204,7 @@ void make_ws(vtgs_plan *p) {
   w.keys_tmp = at<unsigned long long>(b, p->r_keys_tmp);
   w.ids = at<uint32_t>(b, p->r_ids);
   w.slots = p->any_learnable ? at<float>(b, p->r_slots) : nullptr;
+  w.lane_bits = at<unsigned long long>(b, p->r_bits);
   w.t_final = at<float>(b, p->r_tfinal);
   w.last = at<uint32_t>(b, p->r_last);
   w.img = at<float>(b, p->r_img);

@@ -108,6 +108,16 @@ __device__ __forceinline__ float quad(const float4 &e0, float qc, float px, floa
   return q;
 }
 
+// First u64 of the lane bits of chunk c of the batch at list offset `boff`
+// (a multiple of 64) of tile t, wave w of nw, ppt pixels per lane.  Chunks
+// of consecutive tiles never share an index (the tile number is added to
+// the list position / 64), and the index stays below cap / 64 + n_tiles + 1.
+__device__ __forceinline__ int64_t chunk_word(int start, int boff, int c, int t, int w, int nw,
+                                              int ppt) {
+  const int64_t cid = (int64_t)(start >> 6) + (boff >> 6) + c + t;
+  return ((cid * nw + w) * ppt) * kWave;
+}
+
 // The same q from a staged entry whose off-diagonal term is already
 // doubled (e0.w = 2 qb): identical operations, identical bits.
 __device__ __forceinline__ float quad2(const float4 &e0, float qc, float px, float py) {
@@ -239,6 +249,12 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
       unsigned long long own[PPT];
 #pragma unroll
       for (int k = 0; k < PPT; k++) own[k] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
+      {
+        // kept for the backward, which replays the same chunks
+        unsigned long long *dst = ws.lane_bits + chunk_word(start, b - start, c, t, w, NW, PPT);
+#pragma unroll
+        for (int k = 0; k < PPT; k++) dst[k * kWave + lane_id()] = own[k];
+      }
       // 2. each lane composites its own entries in list order
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
@@ -391,18 +407,21 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   const float vfx = vw.fx, vfy = vw.fy;
 
   // batches walk the list from the block's last contributor towards the front
+  // batches on the forward's grid (start + multiples of BATCH), so each
+  // 64-entry chunk is the forward's chunk and its lane bits apply
+  const int nbat = (stop - start + BATCH - 1) / BATCH;
   BwdEntry st[PER];
-  {
-    const int lo = max(start, stop - BATCH);
+  if (nbat > 0) {
+    const int lo = start + (nbat - 1) * BATCH;
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
       if (i < BATCH && lo + i < stop) load_bwd_entry<kSlots>(ws, vw, ws.ids[lo + i], tx, ty, st[k]);
     }
   }
-  for (int hi = stop; hi > start; hi -= BATCH) {
-    const int lo = max(start, hi - BATCH);
-    const int nb = hi - lo;
+  for (int bi = nbat - 1; bi >= 0; bi--) {
+    const int lo = start + bi * BATCH;
+    const int nb = min(stop, lo + BATCH) - lo;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; k++) {
@@ -427,12 +446,12 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       }
     }
     __syncthreads();
-    {
-      const int nlo = max(start, lo - BATCH);
+    if (bi > 0) {  // the batch below is a full one
+      const int nlo = lo - BATCH;
 #pragma unroll
       for (int k = 0; k < PER; k++) {
         const int i = threadIdx.x + k * NT;
-        if (i < BATCH && nlo + i < lo) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
+        if (i < BATCH) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
       }
     }
     // this wave's entries, last to first, below its own last contributor
@@ -442,35 +461,21 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
       if (top < kWave) m &= (1ull << top) - 1ull;
       if (m == 0ull) continue;
-      // 1. which of the chunk's entries each of this lane's pixels composited
-      uint32_t own_lo[PPT], own_hi[PPT];
+      // 1. the entries of this chunk that reached each of this lane's pixels
+      // in the forward, cut at the pixel's last contributor
+      unsigned long long own[PPT];
+      {
+        const unsigned long long *src =
+            ws.lane_bits + chunk_word(start, lo - start, c, t, w, NW, PPT);
+        const int base = lo - start + c * kWave;
 #pragma unroll
-      for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
-      for (int h = 0; h < 2; h++) {
-        uint32_t mh = (uint32_t)(m >> (32 * h));
-        while (mh) {  // two entries per step, both loads issued first
-          const int ja = __builtin_ctz(mh);
-          mh &= mh - 1u;
-          const bool hb = mh != 0u;
-          const int jb = hb ? __builtin_ctz(mh) : ja;
-          mh &= hb ? mh - 1u : mh;
-          const int sa = c * kWave + 32 * h + ja, sb = c * kWave + 32 * h + jb;
-          const float4 a0 = e0s[sa], b0 = e0s[sb];
-          const float aq = e1s[sa].x, bq = e1s[sb].x;
-          const int ia = lo + sa - start, ib = lo + sb - start;
-#pragma unroll
-          for (int k = 0; k < PPT; k++) {
-            const float qa = quad2(a0, aq, px[k], py[k]);
-            const float qb = quad2(b0, bq, px[k], py[k]);
-            const uint32_t bits = ((ia < (int)last[k] && qa <= qcut) ? (1u << ja) : 0u) |
-                                  ((ib < (int)last[k] && qb <= qcut) ? (1u << jb) : 0u);
-            if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
-          }
+        for (int k = 0; k < PPT; k++) {
+          const int lim_k = (int)last[k] - base;
+          const unsigned long long below =
+              lim_k >= kWave ? ~0ull : (lim_k <= 0 ? 0ull : (1ull << lim_k) - 1ull);
+          own[k] = src[k * kWave + lane_id()] & below & m;
         }
       }
-      unsigned long long own[PPT];
-#pragma unroll
-      for (int k = 0; k < PPT; k++) own[k] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
       // 2. each lane replays its own entries, last to first
 #pragma unroll
       for (int k = 0; k < PPT; k++) {

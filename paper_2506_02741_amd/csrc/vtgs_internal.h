@@ -89,6 +89,7 @@ struct Ws {
   // pairs
   unsigned long long *keys;    // [cap] (depth bits << 32) | view-local id
   unsigned long long *keys_tmp;// [cap]
+  unsigned long long *lane_bits;// [(cap/64 + n_tiles + 2) * lane_bits_per_chunk(tile)]
   uint32_t *ids;               // [cap] sorted view-local ids
   float *slots;                // [cap][5] per (record, tile) gradient partials
   // per pixel
@@ -228,6 +229,11 @@ __device__ __forceinline__ int find_view_by_tile(const Ws &ws, int t) {
 // ---------------------------------------------------------------------------
 // launchers (each kernel source file implements its own)
 // ---------------------------------------------------------------------------
+// u64 words of lane bits per 64-entry chunk of a tile list: one per lane
+// and pixel of every wave of the tile's block (tile 8: 1 wave of 64 pixels;
+// 16: 4 waves; 32: 4 waves with 4 pixels per lane).
+inline int lane_bits_per_chunk(int tile) { return tile == 8 ? 64 : tile == 16 ? 256 : 1024; }
+
 hipError_t launch_ingest_count(const float *depth, const uint8_t *mask, int H, int W, int s,
                                uint32_t *scratch, int32_t *count, hipStream_t st);
 hipError_t launch_ingest_fill(const float *depth, const float *rgb, const uint8_t *mask, int H,

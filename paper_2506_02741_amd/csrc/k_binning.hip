@@ -310,45 +310,21 @@ __device__ __forceinline__ uint32_t field8(unsigned long long lo, unsigned long 
   return (uint32_t)(v >> (8 * (d & 7))) & 0xffu;
 }
 
-// Stable LSD radix sort of the NT * E keys of a block, 4-bit digits, only
-// over the digits where the first n keys differ (keys past n must be
-// ~0ull; being maximal and last they stay last).  Thread t holds keys
-// t*E .. t*E+E-1 in registers ("blocked" order).  Per pass each thread
-// counts its keys per digit in 8-bit fields, a DPP wave scan of the counts
-// (as 16-bit fields) and a pass over the wave totals in LDS give each thread
-// its start in every digit bucket, and the keys are scattered through `buf`
-// in thread-then-register order, which keeps the sort stable.  On return
-// buf[0 .. NT*E) holds the sorted keys.
+// Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
+// of the NT * E keys of a block.  Thread t holds keys t*E .. t*E+E-1 in
+// registers ("blocked" order).  Per pass each thread counts its keys per
+// digit in 8-bit fields, a DPP wave scan of the counts (as 16-bit fields)
+// and a pass over the wave totals in LDS give each thread its start in
+// every digit bucket, and the keys are scattered through `buf` in
+// thread-then-register order, which keeps each pass stable.  On return
+// buf[0 .. NT*E) and the registers hold the keys in the new order.
 template <int NT, int E>
-__device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long long *buf,
-                               uint32_t (*wsum)[8], unsigned long long *red) {
+__device__ void radix_passes(unsigned long long (&k)[E], unsigned long long digits,
+                             unsigned long long *buf, uint32_t (*wsum)[8]) {
   constexpr int NW = NT / kWave;
   const int t = threadIdx.x, l = lane_id(), w = t / kWave;
-  unsigned long long orv = 0ull, andv = ~0ull;
-#pragma unroll
-  for (int e = 0; e < E; e++)
-    if (t * E + e < n) { orv |= k[e]; andv &= k[e]; }
-  for (int o = 32; o > 0; o >>= 1) {
-    orv |= __shfl_xor(orv, o);
-    andv &= __shfl_xor(andv, o);
-  }
-  if (l == 0) { red[2 * w] = orv; red[2 * w + 1] = andv; }
-  __syncthreads();
-  orv = 0ull; andv = ~0ull;
-#pragma unroll
-  for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
-  const unsigned long long diff = orv ^ andv;
-  int last_shift = -1;
-  for (int sh = 0; sh < 64; sh += 4)
-    if ((diff >> sh) & 15ull) last_shift = sh;
-  if (last_shift < 0) {  // nothing to order
-#pragma unroll
-    for (int e = 0; e < E; e++) buf[t * E + e] = k[e];
-    __syncthreads();
-    return;
-  }
-  for (int sh = 0; sh <= last_shift; sh += 4) {
-    if (((diff >> sh) & 15ull) == 0ull) continue;
+  for (int sh = 0; sh < 64; sh += 4) {
+    if (((digits >> sh) & 15ull) == 0ull) continue;
     int dg[E];
     unsigned long long clo = 0ull, chi = 0ull;
 #pragma unroll
@@ -410,6 +386,69 @@ __device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long 
   }
 #pragma unroll
   for (int e = 0; e < E; e++) buf[t * E + e] = k[e];
+  __syncthreads();
+}
+
+// Sort of the NT * E keys (depth bits << 32 | id) of a block; the first n
+// are the tile's, the rest ~0ull (maximal, and last, so they stay last).
+// Depth first: radix passes over the depth nibbles that vary.  Keys of equal
+// depth then form runs ordered by fill position; each run is put in id
+// order by one thread (insertion sort), unless some run is longer than 64,
+// in which case every varying nibble (id included) is sorted by radix
+// instead.  Either way buf[0 .. n) ends in ascending (depth, id) order.
+template <int NT, int E>
+__device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long long *buf,
+                               uint32_t (*wsum)[8], unsigned long long *red) {
+  constexpr int NW = NT / kWave;
+  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
+  unsigned long long orv = 0ull, andv = ~0ull;
+#pragma unroll
+  for (int e = 0; e < E; e++)
+    if (t * E + e < n) { orv |= k[e]; andv &= k[e]; }
+  for (int o = 32; o > 0; o >>= 1) {
+    orv |= __shfl_xor(orv, o);
+    andv &= __shfl_xor(andv, o);
+  }
+  if (l == 0) { red[2 * w] = orv; red[2 * w + 1] = andv; }
+  __syncthreads();
+  orv = 0ull; andv = ~0ull;
+#pragma unroll
+  for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
+  const unsigned long long diff = orv ^ andv;
+  radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum);
+  // runs of equal depth among the first n keys, found from their first key
+  bool long_run = false;
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int i = t * E + e;
+    if (i + 1 >= n) continue;
+    const uint32_t z = (uint32_t)(buf[i] >> 32);
+    if ((uint32_t)(buf[i + 1] >> 32) != z || (i > 0 && (uint32_t)(buf[i - 1] >> 32) == z)) continue;
+    int len = 2;
+    while (i + len < n && len <= 64 && (uint32_t)(buf[i + len] >> 32) == z) len++;
+    long_run = long_run || len > 64;
+  }
+  if (__syncthreads_or(long_run)) {
+    radix_passes<NT, E>(k, diff & 0x00000000FFFFFFFFull, buf, wsum);
+    radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum);
+    return;
+  }
+  // insertion sort of every run by id (the runs are disjoint)
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int i = t * E + e;
+    if (i + 1 >= n) continue;
+    const uint32_t z = (uint32_t)(buf[i] >> 32);
+    if ((uint32_t)(buf[i + 1] >> 32) != z || (i > 0 && (uint32_t)(buf[i - 1] >> 32) == z)) continue;
+    int len = 2;
+    while (i + len < n && (uint32_t)(buf[i + len] >> 32) == z) len++;
+    for (int a = i + 1; a < i + len; a++) {
+      const unsigned long long v = buf[a];
+      int b = a - 1;
+      while (b >= i && buf[b] > v) { buf[b + 1] = buf[b]; b--; }
+      buf[b + 1] = v;
+    }
+  }
   __syncthreads();
 }
 

@@ -451,3 +451,34 @@ def test_long_tile_lists_bitwise(R, orc, zoom, tile):
     assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
     ref = orc.render(ov, okfs, prm, margin=MARGIN)
     check_images(*imgs, ref, max_marginal=2e-2)
+
+
+@pytest.mark.parametrize("case", ["long_runs", "short_runs"])
+def test_tile_lists_with_depth_ties(R, orc, case):
+    """Equal depths are ordered by id: a constant-depth back plane seen from
+    its own keyframe (runs of equal depth longer than 64 entries) and a
+    keyframe whose column pairs share depths (runs of two)."""
+    from paper_2506_02741_amd import synth
+    if case == "long_runs":
+        f, colors = synth.toy_scene(0)
+        depth, rgb, cam, pose = f.depth, colors, f.cam.as_tuple(), f.pose
+    else:
+        cam_, frames, _ = room_frames(5, 80, 60)
+        fr = frames[0]
+        depth = fr.depth.copy()
+        depth[:, 1::2] = depth[:, 0::2]
+        rgb, cam, pose = fr.rgb, cam_.as_tuple(), fr.pose
+    k = R.Keyframe.ingest(depth, rgb, cam, pose)
+    plan = R.Plan([k], [R.View(cam, pose)], R.params(tile=16))
+    imgs = plan.render_fwd()
+    st = plan.debug_state()
+    assert plan.status()[0] == 0
+    okf = orc.ingest(depth, rgb, fx=cam[0], cam=cam, pose=pose)
+    ov = orc.ViewSpec(cam, pose)
+    keys, vals, ranges = orc.tile_lists(ov, [okf], orc.params(tile=16))
+    z = keys & np.uint64(0xFFFFFFFF)
+    ties = sum(int(np.any(z[s + 1:e] == z[s:e - 1])) for s, e in ranges if e - s > 1)
+    assert ties > 0
+    assert same_ranges(np_(st["ranges"]), ranges)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+    check_images(*imgs, orc.render(ov, [okf], margin=MARGIN), max_marginal=2e-2)

@@ -217,7 +217,7 @@ int vtgs_map_step(vtgs_plan *plan, const vtgs_map_cfg *cfg, int32_t *step, float
  * enable == 0 stops, synchronises those events and writes, per stage index
  * s < VTGS_N_STAGES, the summed milliseconds ms[s] and launches count[s]
  * (either array may be NULL).  vtgs_stage_name(s) names stage s. */
-#define VTGS_N_STAGES 11
+#define VTGS_N_STAGES 10
 const char *vtgs_stage_name(int32_t stage);
 int vtgs_plan_timing(vtgs_plan *plan, int32_t enable, double *ms, int64_t *count);
 

@@ -18,7 +18,7 @@ VTGS_E_HIP = -2
 VTGS_E_WORKSPACE = -3
 VTGS_E_CAPACITY = -4
 VTGS_E_NONFINITE = -5
-VTGS_N_STAGES = 11
+VTGS_N_STAGES = 10
 
 
 class vtgs_camera(C.Structure):

@@ -88,8 +88,8 @@ struct vtgs_plan {
   bool any_learnable = false;
   // workspace layout
   Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
-      r_ranges, r_keys, r_keys_tmp, r_ids, r_slots, r_bits, r_tfinal, r_last, r_img, r_gimg,
-      r_twist, r_loss, r_ssim_map, r_ssim_part;
+      r_ranges, r_long, r_keys, r_keys_tmp, r_ids, r_slots, r_bits, r_tfinal, r_last, r_img,
+      r_gimg, r_twist, r_loss, r_ssim_map, r_ssim_part;
   int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
   int64_t ws_bytes = 0;
   // binding
@@ -149,6 +149,7 @@ void layout(vtgs_plan *p) {
   take(p->r_tcount, nt * 4);
   take(p->r_tfill, nt * 4);
   take(p->r_ranges, nt * 8);
+  take(p->r_long, nt * 4);
   take(p->r_keys, cap * 8);
   take(p->r_keys_tmp, cap * 8);
   take(p->r_ids, cap * 4);
@@ -160,7 +161,7 @@ void layout(vtgs_plan *p) {
   take(p->r_last, P * 4);
   take(p->r_img, 5 * P * 4);
   take(p->r_gimg, 5 * P * 4);
-  take(p->r_twist, nt * 24);
+  take(p->r_twist, nt * 32);
   take(p->r_loss, nv * (int64_t)p->loss_blocks * 16);
   take(p->r_ssim_map, 9 * P * 4);
   take(p->r_ssim_part, nv * 3 * (int64_t)p->ssim_gx * p->ssim_gy * 4);
@@ -178,6 +179,9 @@ void make_ws(vtgs_plan *p) {
   w.flags = reinterpret_cast<uint32_t *>(b + p->r_hdr.off);
   w.n_pairs = reinterpret_cast<unsigned long long *>(b + p->r_hdr.off + 8);
   w.iter = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 16);
+  w.n_long = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 24);
+  w.long_next = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 28);
+  w.long_tiles = at<uint32_t>(b, p->r_long);
   char *d = b + p->r_desc.off;
   w.kfs = reinterpret_cast<const DevKF *>(d + p->desc_kf);
   w.views = reinterpret_cast<const DevView *>(d + p->desc_view);
@@ -234,12 +238,12 @@ int check_bound(vtgs_plan *p) {
 }
 
 enum Stage {
-  ST_SETUP, ST_PRE, ST_SCAN, ST_FILL, ST_SORT, ST_FWD, ST_LOSS, ST_RSCAN, ST_BWD, ST_REDUCE,
-  ST_UPDATE, ST_N
+  ST_PRE, ST_SCAN, ST_FILL, ST_SORT, ST_FWD, ST_LOSS, ST_RSCAN, ST_BWD, ST_REDUCE, ST_UPDATE, ST_N
 };
-const char *kStageNames[ST_N] = {"setup",        "preprocess", "scan_tiles",   "fill_keys",
-                                 "sort_tiles",   "composite_fwd", "loss",      "scan_records",
-                                 "composite_bwd", "reduce",     "update"};
+static_assert(ST_N == VTGS_N_STAGES, "stage table");
+const char *kStageNames[ST_N] = {"preprocess",   "scan_tiles",    "fill_keys", "sort_tiles",
+                                 "composite_fwd", "loss",         "scan_records",
+                                 "composite_bwd", "reduce",       "update"};
 
 hipError_t event_at(vtgs_plan *p, size_t i, hipEvent_t *e) {
   while (p->ev_pool.size() <= i) {
@@ -274,8 +278,7 @@ hipError_t event_at(vtgs_plan *p, size_t i, hipEvent_t *e) {
 // The binning pipeline and the forward compositing into (rgb, depth, sil).
 int run_forward(vtgs_plan *p, float *rgb, float *depth, float *sil, hipStream_t st) {
   const Ws &w = p->w;
-  STAGE(p, ST_SETUP, st, launch_setup(w, st));
-  STAGE(p, ST_PRE, st, launch_preprocess(w, st));
+  STAGE(p, ST_PRE, st, launch_preprocess(w, st));  // (+ relative poses)
   STAGE(p, ST_SCAN, st, launch_scan_tiles(w, st));
   STAGE(p, ST_FILL, st, launch_fill_keys(w, st));
   STAGE(p, ST_SORT, st, launch_sort_tiles(w, st));
@@ -290,8 +293,9 @@ int track_iteration(vtgs_plan *p, const vtgs_track_cfg &cfg, float *loss, hipStr
   const Ws &w = p->w;
   const int64_t P = p->P;
   if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
-  STAGE(p, ST_LOSS, st, launch_track_loss(w, cfg, st));
-  STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 1, st));
+  (void)P;
+  // Eq. 1 and its upstream gradient are evaluated by the backward per pixel
+  STAGE(p, ST_BWD, st, launch_composite_bwd(w, nullptr, nullptr, nullptr, 1, st, &cfg));
   STAGE(p, ST_UPDATE, st, launch_track_update(w, cfg, loss, st));
   return VTGS_OK;
 }

@@ -37,25 +37,22 @@ __global__ void k_fill_f32(float *p, float v, int64_t n) {
 }
 
 // M = Tv * Tk^-1 = [Rv Rk^T | tv - (Rv Rk^T) tk], fixed summation order.
-__global__ void k_setup(Ws ws) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  // one more pass of the pipeline: the tracking update writes its loss at
-  // this index, so a captured iteration needs no per-iteration argument
-  if (s == 0) *ws.iter += 1u;
-  if (s >= ws.n_segs) return;
-  DevSeg &sg = ws.segs[s];
-  const float *Tv = ws.views[sg.view].pose;
-  const float *Tk = ws.kfs[sg.kf].pose;
-  float tv[12], tk[12], M[12];
+// Relative pose M = T_v T_k^-1 (3x4, world->camera poses with orthonormal
+// rotations, so T_k^-1 = [R_k^T | -R_k^T t_k]) in a fixed FP32 order.
+__device__ __forceinline__ void relative_pose(const float *Tv, const float *Tk, float *M) {
+  float tv[12], tk[12];
+#pragma unroll
   for (int i = 0; i < 12; i++) { tv[i] = Tv[i]; tk[i] = Tk[i]; }
+#pragma unroll
   for (int i = 0; i < 3; i++)
+#pragma unroll
     for (int j = 0; j < 3; j++)
       M[4 * i + j] = (tv[4 * i + 0] * tk[4 * j + 0] + tv[4 * i + 1] * tk[4 * j + 1]) +
                      tv[4 * i + 2] * tk[4 * j + 2];
+#pragma unroll
   for (int i = 0; i < 3; i++)
     M[4 * i + 3] = tv[4 * i + 3] -
                    ((M[4 * i + 0] * tk[3] + M[4 * i + 1] * tk[7]) + M[4 * i + 2] * tk[11]);
-  for (int i = 0; i < 12; i++) sg.M[i] = M[i];
 }
 
 __device__ __forceinline__ int find_seg(const Ws &ws, int r) {
@@ -111,6 +108,9 @@ __device__ __forceinline__ unsigned long long box_ballot(const WaveBox &b, int j
 
 __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   const int r = blockIdx.x * kNT + threadIdx.x;
+  // one more pass of the pipeline: the tracking update writes its loss at
+  // this index, so a captured iteration needs no per-iteration argument
+  if (r == 0) *ws.iter += 1u;
   const bool active = r < ws.n_rec;
   bool has = false;
   int view = 0, x0 = 1, y0 = 0, x1 = 0, y1 = 0, tiles_x = 1, tile_base = 0;
@@ -118,6 +118,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     const DevSeg &sg = ws.segs[find_seg(ws, r)];
     const DevKF &kf = ws.kfs[sg.kf];
     const DevView &vw = ws.views[sg.view];
+    float M[12];
+    relative_pose(vw.pose, kf.pose, M);
     view = sg.view;
     tiles_x = vw.tiles_x;
     tile_base = vw.tile_base;
@@ -130,7 +132,6 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     const float xk = (((float)u - kf.cx) / kf.fx) * d;
     const float yk = (((float)v - kf.cy) / kf.fy) * d;
     const float zk = d;
-    const float *M = sg.M;
     const float px = ((M[0] * xk + M[1] * yk) + M[2] * zk) + M[3];
     const float py = ((M[4] * xk + M[5] * yk) + M[6] * zk) + M[7];
     const float pz = ((M[8] * xk + M[9] * yk) + M[10] * zk) + M[11];
@@ -194,13 +195,18 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   }
 }
 
+constexpr int kSmallSort = 2048;  // longer tile lists go to the long-list sort
+
 // One block: tile counts -> ranges (clamped to the pair capacity), total
-// pairs, capacity flag; clears the counters for the next pass.
+// pairs, capacity flag; lists longer than kSmallSort are queued for the
+// long-list sort (queue and its cursor reset here); clears the counters for
+// the next pass.
 constexpr int kScanNT = 1024, kScanPer = 8;
 __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
   __shared__ uint32_t lw[kScanNT / kWave];
   __shared__ unsigned long long carry_s;
-  if (threadIdx.x == 0) carry_s = 0;
+  __shared__ uint32_t nlong_s;
+  if (threadIdx.x == 0) { carry_s = 0; nlong_s = 0; }
   __syncthreads();
   for (int base = 0; base < ws.n_tiles; base += kScanNT * kScanPer) {
     const int i0 = base + threadIdx.x * kScanPer;
@@ -219,6 +225,7 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
         const unsigned long long s = pos < (unsigned long long)ws.cap ? pos : ws.cap;
         const unsigned long long e = pos + v[k] < (unsigned long long)ws.cap ? pos + v[k] : ws.cap;
         ws.ranges[i] = make_uint2((uint32_t)s, (uint32_t)e);
+        if (e - s > (unsigned long long)kSmallSort) ws.long_tiles[atomicAdd(&nlong_s, 1u)] = i;
         ws.tile_count[i] = 0;
         ws.tile_fill[i] = 0;
       }
@@ -231,6 +238,8 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
   if (threadIdx.x == 0) {
     *ws.n_pairs = carry_s;
     if (carry_s > (unsigned long long)ws.cap) atomicOr(ws.flags, kFlagCapacity);
+    *ws.n_long = nlong_s;
+    *ws.long_next = 0u;
   }
 }
 
@@ -488,21 +497,39 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
 // so ascending key order is the (depth, id) order.  Each variant handles the
 // tiles whose length lies in (lo_n, hi_n]; longer than NT * E -> global memory.
 template <int NT, int E>
-__global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
+__global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, int queued) {
   constexpr int CAP = NT * E;
   __shared__ unsigned long long buf[CAP];
   __shared__ uint32_t wsum[NT / kWave][8];
   __shared__ unsigned long long red[2 * (NT / kWave)];
+  // short lists: tile = block; long lists: blocks take queued tiles in turn
+  __shared__ int next_s;
+  if (queued && *ws.n_long == 0u) return;  // (one load when nothing is queued)
+  for (int round = 0;; round++) {
+  int tile;
+  if (!queued) {
+    if (round > 0) break;
+    tile = blockIdx.x;
+  } else {
+    if (threadIdx.x == 0) {
+      const uint32_t q = atomicAdd(ws.long_next, 1u);
+      next_s = q < *ws.n_long ? (int)ws.long_tiles[q] : -1;
+    }
+    __syncthreads();
+    tile = next_s;
+    __syncthreads();
+    if (tile < 0) break;
+  }
   // ranges are clamped to the capacity, and every position of a clamped
   // range was written by the fill, so sorting stays in bounds on overflow
-  const uint2 rg = ws.ranges[blockIdx.x];
+  const uint2 rg = ws.ranges[tile];
   const int n = (int)(rg.y - rg.x);
-  if (n <= lo_n || n > hi_n || n <= 0) return;
+  if (n <= lo_n || n > hi_n || n <= 0) continue;
   const unsigned long long *src = ws.keys + rg.x;
   uint32_t *dst = ws.ids + rg.x;
   if (n == 1) {
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
-    return;
+    continue;
   }
   if (n <= CAP / 2) {
     // half the registers per thread when half the capacity suffices
@@ -530,9 +557,9 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n) {
     bitonic_sort(g, n);
     for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)g[i];
   }
+  __syncthreads();  // buf is reused by the block's next tile
+  }
 }
-
-constexpr int kSmallSort = 2048;
 
 // Device-wide exclusive scan of rec_cnt -> rec_off (3 phases).
 constexpr int kRecPer = 8, kRecBlock = kNT * kRecPer;
@@ -609,17 +636,13 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_setup(const Ws &ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(blocks_for(ws.n_segs > 0 ? ws.n_segs : 1, 64)), dim3(64), 0, st,
-                     ws);
+hipError_t launch_preprocess(const Ws &ws, hipStream_t st) {
+  // at least one block: it bumps the pass counter
+  const int64_t nb = ws.n_rec > 0 ? blocks_for(ws.n_rec, kNT) : 1;
+  hipLaunchKernelGGL(k_preprocess, dim3(nb), dim3(kNT), 0, st, ws);
   return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const Ws &ws, hipStream_t st) {
-  if (ws.n_rec == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws);
-  return hipGetLastError();
-}
 
 hipError_t launch_scan_tiles(const Ws &ws, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanNT), 0, st, ws);
@@ -634,9 +657,11 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
   hipLaunchKernelGGL((k_sort_tiles<256, kSmallSort / 256>), dim3(ws.n_tiles), dim3(256), 0, st,
-                     ws, 0, kSmallSort);
-  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(ws.n_tiles), dim3(512), 0, st, ws,
-                     kSmallSort, 0x7fffffff);
+                     ws, 0, kSmallSort, 0);
+  // long lists, queued by the scan: two 512-thread blocks per CU take them
+  // in turn (most views have none, and the launch then ends at once)
+  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(std::min(ws.n_tiles, 512)), dim3(512),
+                     0, st, ws, kSmallSort, 0x7fffffff, 1);
   return hipGetLastError();
 }
 

@@ -46,6 +46,15 @@ namespace {
 
 constexpr float kNegHalfLog2e = -0.72134752044448170368f;  // -log2(e) / 2
 
+// Eq. 1 evaluated inside the tracking backward (on = 0: upstream gradients
+// come from the caller's arrays).
+struct TrackArgs {
+  float alpha, beta, sil_thr;
+  int on;
+};
+
+__device__ __forceinline__ float sgn(float x) { return (float)((x > 0.f) - (x < 0.f)); }
+
 template <int TILE>
 struct Shape {
   static constexpr int NT = TILE == 8 ? 64 : 256;
@@ -343,7 +352,7 @@ __device__ __forceinline__ void load_bwd_entry(const Ws &ws, const DevView &vw, 
 template <int TILE, int BATCH, int MODE>
 __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_rgb,
                                                          const float *g_depth,
-                                                         const float *g_sil) {
+                                                         const float *g_sil, TrackArgs tr) {
   constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT;
   constexpr int NW = NT / kWave;
   constexpr int PER = (BATCH + NT - 1) / NT;
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   __shared__ uint32_t slot_s[AB];
   __shared__ float acc[NW][5][AB];
   __shared__ int maxlast_s;
-  __shared__ float red_s[NW][6];
+  __shared__ float red_s[NW][7];
   __shared__ unsigned long long masks[NW][NCH];
 
   const int t = blockIdx.x;
@@ -376,6 +385,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   float SB[PPT];
   uint32_t last[PPT];
   uint32_t mylast = 0;
+  float lsum = 0.f;  // this lane's share of the tile's Eq. 1 loss
 #pragma unroll
   for (int k = 0; k < PPT; k++) {
     int x, y;
@@ -386,11 +396,33 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
     const int64_t p = vw.pix_off + (int64_t)(oy + y) * vw.width + (ox + x);
     T[k] = valid ? ws.t_final[p] : 1.f;
     last[k] = valid ? ws.last[p] : 0u;
-    gC0[k] = (valid && g_rgb) ? g_rgb[p] : 0.f;
-    gC1[k] = (valid && g_rgb) ? g_rgb[P + p] : 0.f;
-    gC2[k] = (valid && g_rgb) ? g_rgb[2 * P + p] : 0.f;
-    gD[k] = (valid && g_depth) ? g_depth[p] : 0.f;
-    gS[k] = (valid && g_sil) ? g_sil[p] : 0.f;
+    if (tr.on) {
+      // Eq. 1: alpha W |V - V'| + beta W |D - D'|, W = vis & (D > 0) & (S' > thr)
+      const int64_t lp = p - vw.pix_off;
+      const int64_t Pv = (int64_t)vw.width * vw.height;
+      float od = 0.f;
+      bool W = false;
+      if (valid) {
+        od = vw.obs_depth[lp];
+        W = (!vw.vis || vw.vis[lp] != 0) && od > 0.f && ws.img[4 * P + p] > tr.sil_thr;
+      }
+      const float r0 = valid ? vw.obs_rgb[lp] - ws.img[p] : 0.f;
+      const float r1 = valid ? vw.obs_rgb[Pv + lp] - ws.img[P + p] : 0.f;
+      const float r2 = valid ? vw.obs_rgb[2 * Pv + lp] - ws.img[2 * P + p] : 0.f;
+      const float rd = valid ? od - ws.img[3 * P + p] : 0.f;
+      gC0[k] = W ? -tr.alpha * sgn(r0) : 0.f;
+      gC1[k] = W ? -tr.alpha * sgn(r1) : 0.f;
+      gC2[k] = W ? -tr.alpha * sgn(r2) : 0.f;
+      gD[k] = W ? -tr.beta * sgn(rd) : 0.f;
+      gS[k] = 0.f;
+      lsum += W ? tr.alpha * ((fabsf(r0) + fabsf(r1)) + fabsf(r2)) + tr.beta * fabsf(rd) : 0.f;
+    } else {
+      gC0[k] = (valid && g_rgb) ? g_rgb[p] : 0.f;
+      gC1[k] = (valid && g_rgb) ? g_rgb[P + p] : 0.f;
+      gC2[k] = (valid && g_rgb) ? g_rgb[2 * P + p] : 0.f;
+      gD[k] = (valid && g_depth) ? g_depth[p] : 0.f;
+      gS[k] = (valid && g_sil) ? g_sil[p] : 0.f;
+    }
     SB[k] = fmaf(gC0[k], ws.bg[0], fmaf(gC1[k], ws.bg[1], gC2[k] * ws.bg[2]));
     mylast = max(mylast, last[k]);
   }
@@ -564,17 +596,20 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
     }
   }
   if (kTwist) {
+    // per tile: the six twist sums and (tracking) the Eq. 1 loss
 #pragma unroll
     for (int c = 0; c < 6; c++) {
       const float s = wave_sum(tw[c]);
       if (lane_id() == 0) red_s[w][c] = s;
     }
+    const float ls = wave_sum(lsum);
+    if (lane_id() == 0) red_s[w][6] = ls;
     __syncthreads();
-    if (threadIdx.x < 6) {
+    if (threadIdx.x < 7) {
       float s = 0.f;
 #pragma unroll
       for (int ww = 0; ww < NW; ww++) s += red_s[ww][threadIdx.x];
-      ws.twist_part[6 * (int64_t)t + threadIdx.x] = s;
+      ws.twist_part[8 * (int64_t)t + threadIdx.x] = s;
     }
   }
 }
@@ -588,12 +623,12 @@ hipError_t fwd_launch(const Ws &ws, float *rgb, float *depth, float *sil, hipStr
 
 template <int TILE, int BATCH>
 hipError_t bwd_launch(const Ws &ws, const float *g_rgb, const float *g_depth, const float *g_sil,
-                      int mode, hipStream_t st) {
+                      int mode, hipStream_t st, TrackArgs tr) {
   const dim3 g(ws.n_tiles), b(Shape<TILE>::NT);
   switch (mode) {
-    case 1: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 1>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
-    case 2: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 2>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
-    case 3: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 3>), g, b, 0, st, ws, g_rgb, g_depth, g_sil); break;
+    case 1: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 1>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
+    case 2: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 2>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
+    case 3: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 3>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -611,11 +646,11 @@ hipError_t fwd_tile(const Ws &ws, float *rgb, float *depth, float *sil, hipStrea
 
 template <int TILE>
 hipError_t bwd_tile(const Ws &ws, const float *a, const float *b, const float *c, int mode,
-                    hipStream_t st) {
+                    hipStream_t st, TrackArgs tr) {
   switch (ws.batch) {
-    case 128: return bwd_launch<TILE, 128>(ws, a, b, c, mode, st);
-    case 256: return bwd_launch<TILE, 256>(ws, a, b, c, mode, st);
-    case 512: return bwd_launch<TILE, 512>(ws, a, b, c, mode, st);
+    case 128: return bwd_launch<TILE, 128>(ws, a, b, c, mode, st, tr);
+    case 256: return bwd_launch<TILE, 256>(ws, a, b, c, mode, st, tr);
+    case 512: return bwd_launch<TILE, 512>(ws, a, b, c, mode, st, tr);
   }
   return hipErrorInvalidValue;
 }
@@ -634,12 +669,18 @@ hipError_t launch_composite_fwd(const Ws &ws, float *rgb, float *depth, float *s
 }
 
 hipError_t launch_composite_bwd(const Ws &ws, const float *g_rgb, const float *g_depth,
-                                const float *g_sil, int mode, hipStream_t st) {
+                                const float *g_sil, int mode, hipStream_t st,
+                                const vtgs_track_cfg *track) {
   if (ws.n_tiles == 0) return hipSuccess;
+  TrackArgs tr{0.f, 0.f, 0.f, 0};
+  if (track) {
+    if (mode != 1) return hipErrorInvalidValue;
+    tr = TrackArgs{track->alpha, track->beta, track->sil_thr, 1};
+  }
   switch (ws.tile) {
-    case 8: return bwd_tile<8>(ws, g_rgb, g_depth, g_sil, mode, st);
-    case 16: return bwd_tile<16>(ws, g_rgb, g_depth, g_sil, mode, st);
-    case 32: return bwd_tile<32>(ws, g_rgb, g_depth, g_sil, mode, st);
+    case 8: return bwd_tile<8>(ws, g_rgb, g_depth, g_sil, mode, st, tr);
+    case 16: return bwd_tile<16>(ws, g_rgb, g_depth, g_sil, mode, st, tr);
+    case 32: return bwd_tile<32>(ws, g_rgb, g_depth, g_sil, mode, st, tr);
   }
   return hipErrorInvalidValue;
 }

@@ -1,8 +1,8 @@
 // Losses and optimiser steps around the splat.
 //
-//  track_loss   Eq. 1 (Sec. 3.3): alpha sum W |V - V'| + beta sum W |D - D'|
-//               with W = vis & (D > 0) & (S' > sil_thr) held fixed; writes
-//               dL/dV', dL/dD' and per-block loss sums
+//  (Eq. 1 itself, alpha sum W |V - V'| + beta sum W |D - D'| with
+//  W = vis & (D > 0) & (S' > sil_thr) held fixed, is evaluated per pixel by
+//  the tracking backward, which also keeps each tile's loss)
 //  twist_reduce per view, the tiles' twist partials summed in a fixed order
 //  track_update twist reduce + Adam on the twist (lr_trans on rho, lr_rot on
 //               phi; App. A) + pose <- exp(step^) pose
@@ -38,46 +38,20 @@ __device__ __forceinline__ float block_sum(float x, float *lds) {
   return t;
 }
 
-__global__ __launch_bounds__(kNT) void k_track_loss(Ws ws, vtgs_track_cfg cfg) {
-  __shared__ float lds[kNT / kWave];
-  const int v = blockIdx.y;
-  const DevView &vw = ws.views[v];
-  const int64_t Pv = (int64_t)vw.width * vw.height;
-  const int64_t lp = (int64_t)blockIdx.x * kNT + threadIdx.x;
-  const int64_t P = ws.P;
-  float l = 0.f;
-  if (lp < Pv) {
-    const int64_t p = vw.pix_off + lp;
-    const float od = vw.obs_depth[lp];
-    const bool W = (!vw.vis || vw.vis[lp] != 0) && od > 0.f && ws.img[4 * P + p] > cfg.sil_thr;
-    for (int c = 0; c < 3; c++) {
-      const float r = vw.obs_rgb[c * Pv + lp] - ws.img[c * P + p];
-      if (W) l += cfg.alpha * fabsf(r);
-      ws.gimg[c * P + p] = W ? -cfg.alpha * sgnf(r) : 0.f;
-    }
-    const float rd = od - ws.img[3 * P + p];
-    if (W) l += cfg.beta * fabsf(rd);
-    ws.gimg[3 * P + p] = W ? -cfg.beta * sgnf(rd) : 0.f;
-  }
-  const float s = block_sum(l, lds);
-  if (threadIdx.x == 0) ws.loss_part[4 * ((int64_t)v * ws.loss_blocks + blockIdx.x)] = s;
-}
-
-// Sum of the view's tile partials (6 floats each) and loss partials.
+// Sum of the view's tile partials (6 twist floats and the tile's Eq. 1 loss,
+// at a stride of 8) in a fixed order.
 __device__ __forceinline__ void reduce_view(const Ws &ws, int v, float *g6, float *loss,
                                            float *lds) {
   const DevView &vw = ws.views[v];
   float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int i = threadIdx.x; i < vw.n_tiles; i += blockDim.x)
-    for (int c = 0; c < 6; c++) acc[c] += ws.twist_part[6 * (int64_t)(vw.tile_base + i) + c];
-  for (int c = 0; c < 6; c++) g6[c] = block_sum(acc[c], lds);
-  if (loss) {
-    const int nb = (int)((((int64_t)vw.width * vw.height) + kNT - 1) / kNT);
-    float l = 0.f;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x)
-      l += ws.loss_part[4 * ((int64_t)v * ws.loss_blocks + i)];
-    *loss = block_sum(l, lds);
+  float l = 0.f;
+  for (int i = threadIdx.x; i < vw.n_tiles; i += blockDim.x) {
+    const float *tp = ws.twist_part + 8 * (int64_t)(vw.tile_base + i);
+    for (int c = 0; c < 6; c++) acc[c] += tp[c];
+    l += tp[6];
   }
+  for (int c = 0; c < 6; c++) g6[c] = block_sum(acc[c], lds);
+  if (loss) *loss = block_sum(l, lds);
 }
 
 __global__ __launch_bounds__(kNT) void k_twist_reduce(Ws ws, float *g_twist) {
@@ -386,10 +360,6 @@ __global__ void k_step_inc(int32_t *step) { *step += 1; }
 
 }  // namespace
 
-hipError_t launch_track_loss(const Ws &ws, const vtgs_track_cfg &cfg, hipStream_t st) {
-  hipLaunchKernelGGL(k_track_loss, dim3(ws.loss_blocks, ws.n_views), dim3(kNT), 0, st, ws, cfg);
-  return hipGetLastError();
-}
 
 hipError_t launch_twist_reduce(const Ws &ws, float *g_twist, hipStream_t st) {
   hipLaunchKernelGGL(k_twist_reduce, dim3(ws.n_views), dim3(kNT), 0, st, ws, g_twist);

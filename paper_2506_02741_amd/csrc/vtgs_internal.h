@@ -64,7 +64,10 @@ struct Ws {
   // header
   uint32_t *flags;
   unsigned long long *n_pairs;
-  uint32_t *iter;              // tracking iteration counter (bumped by setup)
+  uint32_t *iter;              // tracking iteration counter (bumped by preprocess)
+  uint32_t *n_long;            // tiles with lists longer than the short-list sort takes
+  uint32_t *long_next;         // cursor of the long-list sort over long_tiles
+  uint32_t *long_tiles;        // [n_tiles] those tiles (written by the tile scan)
   // descriptors
   const DevKF *kfs;
   const DevView *views;
@@ -244,7 +247,6 @@ int64_t ingest_scratch_words(int H, int W, int s);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
-hipError_t launch_setup(const Ws &ws, hipStream_t st);
 hipError_t launch_preprocess(const Ws &ws, hipStream_t st);
 hipError_t launch_scan_tiles(const Ws &ws, hipStream_t st);
 hipError_t launch_fill_keys(const Ws &ws, hipStream_t st);
@@ -253,12 +255,15 @@ hipError_t launch_scan_records(const Ws &ws, hipStream_t st);
 hipError_t launch_composite_fwd(const Ws &ws, float *rgb, float *depth, float *sil,
                                 hipStream_t st);
 // mode bit 0: twist partials per tile, bit 1: per-(record, tile) slots
+// mode 1: twist, 2: slots, 3: both.  track (mode 1 only, else NULL): the
+// upstream gradient is Eq. 1's, evaluated per pixel from the internal images
+// and the views' observations (g_* ignored), and each tile's loss is kept.
 hipError_t launch_composite_bwd(const Ws &ws, const float *g_rgb, const float *g_depth,
-                                const float *g_sil, int mode, hipStream_t st);
+                                const float *g_sil, int mode, hipStream_t st,
+                                const vtgs_track_cfg *track = nullptr);
 hipError_t launch_twist_reduce(const Ws &ws, float *g_twist, hipStream_t st);
 // max_n: largest Gaussian count of a learnable keyframe
 hipError_t launch_gather(const Ws &ws, int max_n, hipStream_t st);
-hipError_t launch_track_loss(const Ws &ws, const vtgs_track_cfg &cfg, hipStream_t st);
 hipError_t launch_track_update(const Ws &ws, const vtgs_track_cfg &cfg, float *loss,
                                hipStream_t st);
 hipError_t launch_map_loss(const Ws &ws, const vtgs_map_cfg &cfg, hipStream_t st);

@@ -273,7 +273,7 @@ def uneven_run(reps):
                 speedup=single_s / tuned_s, generation_s=gen_s)
 
 
-def serving_run(seconds, rate, n_sections, budget_gib, seed=4):
+def serving_run(seconds, rate, n_sections, budget_gib, seed=4, low_rate=0.0):
     """Poisson render/track requests against a device-resident map of
     n_sections x 10 keyframes at 1200x680, stride 2.  The map is built from
     3 ray-cast sections replicated on the device up to n_sections (a stand-in
@@ -318,16 +318,32 @@ def serving_run(seconds, rate, n_sections, budget_gib, seed=4):
     def obs_for(sec, cam, key):
         _, rgb, depth = obs[key]
         return rgb, depth
-    trace = serve.poisson_trace(np.random.default_rng(seed + 1), rate, seconds, n_sections, cams,
-                                poses_for, obs_for)
-    srv = serve.Server(kfs, sections, budget_bytes=int(budget_gib * (1 << 30)), max_active=64)
-    # warm the kernels and the allocator on a short prefix
-    warm = serve.Server(kfs, sections, budget_bytes=int(budget_gib * (1 << 30)), max_active=64)
-    warm.run_trace(serve.poisson_trace(np.random.default_rng(seed + 2), rate, 0.3, n_sections, cams,
-                                       poses_for, obs_for), realtime=False)
-    rep = srv.run_trace(trace, realtime=True)
+    budget = int(budget_gib * (1 << 30))
+
+    def run(r, sd, warm_first):
+        """One server on a fresh allocator state; freed before returning."""
+        if warm_first:   # kernels and allocator warmed on a short prefix
+            w = serve.Server(kfs, sections, budget_bytes=budget, max_active=64)
+            w.run_trace(serve.poisson_trace(np.random.default_rng(seed + 2), r, 0.3, n_sections,
+                                            cams, poses_for, obs_for), realtime=False)
+            del w
+        srv = serve.Server(kfs, sections, budget_bytes=budget, max_active=64)
+        out = srv.run_trace(serve.poisson_trace(np.random.default_rng(sd), r, seconds, n_sections,
+                                                cams, poses_for, obs_for), realtime=True)
+        out["peak_admitted_gib"] = srv.peak_mem / (1 << 30)
+        del srv
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out
+    low = run(low_rate, seed + 3, True) if low_rate > 0 else None
+    rep = run(rate, seed + 1, low is None)
+    if low is not None:
+        rep["at_lower_rate"] = dict(offered_req_per_s=low_rate, **{
+            k: low[k] for k in ("requests", "req_per_s", "mpix_per_s", "p50_ms", "p99_ms",
+                                "render_p50_ms", "render_p99_ms", "track_p50_ms", "track_p99_ms",
+                                "mean_batch", "host_s", "device_wait_s", "seconds")})
     rep.update(offered_req_per_s=rate, map_gaussians=n_gauss, sections=n_sections,
-               keyframes=len(kfs), budget_gib=budget_gib, peak_admitted_gib=srv.peak_mem / (1 << 30),
+               keyframes=len(kfs), budget_gib=budget_gib,
                generation_s=gen_s,
                workload="Poisson %g req/s for %g s, 60%% render / 40%% 20-iteration track, "
                         "resolutions 320x240/640x480/1200x680, map of %d sections x 10 keyframes "
@@ -352,6 +368,8 @@ def main():
                          "traffic for scaling hardware byte counters)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-rate-low", type=float, default=60.0,
+                    help="a second, lower offered rate (0: skip)")
     ap.add_argument("--serve-sections", type=int, default=30)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     args = ap.parse_args()
@@ -446,7 +464,7 @@ def main():
     if not args.no_serving:
         log("bench: serving %g s at %g req/s" % (args.serve_seconds, args.serve_rate))
         serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_sections,
-                              args.serve_budget_gib)
+                              args.serve_budget_gib, low_rate=args.serve_rate_low)
 
     out = dict(metric="fwd+bwd Mpix/s at 640x480 vs 1-view/launch; p50/p99 render-request latency",
                value=value, unit="Mpix/s", n_gpus=1,

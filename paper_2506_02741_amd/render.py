@@ -174,11 +174,16 @@ def map_cfg(rho=0.8, tau=0.2, sigma=1.0, lr_color=0.0025, lr_opacity=0.05, lr_ra
     return _lib.vtgs_map_cfg(rho, tau, sigma, lr_color, lr_opacity, lr_radius)
 
 
+def keyframe_array(keyframes):
+    """The C descriptors of a keyframe list (vtgs_keyframe[n])."""
+    return (_lib.vtgs_keyframe * max(len(keyframes), 1))(*[k.cstruct() for k in keyframes])
+
+
 class Plan:
     """A batch of views over keyframes, bound to a device workspace."""
 
     def __init__(self, keyframes, views, prm=None, pair_capacity=0, device=None, stream=None,
-                 workspace=None, bind=True):
+                 workspace=None, bind=True, kf_array=None):
         self.L = load()
         self.keyframes = list(keyframes)
         # the descriptors capture the gradient buffers: create them first
@@ -188,7 +193,9 @@ class Plan:
         self.views = list(views)
         self.prm = prm if prm is not None else params()
         self.device = _dev(device)
-        kfa = (_lib.vtgs_keyframe * max(len(self.keyframes), 1))(*[k.cstruct() for k in self.keyframes])
+        # kf_array: the keyframes' descriptors built once by a caller that
+        # plans over the same keyframes many times (their buffers unchanged)
+        kfa = kf_array if kf_array is not None else keyframe_array(self.keyframes)
         va = (_lib.vtgs_view * len(self.views))(*[v.cstruct() for v in self.views])
         h = C.c_void_p()
         check(self.L.vtgs_plan_create(kfa, len(self.keyframes), va, len(self.views),

@@ -74,6 +74,11 @@ class Server:
             self.s_track = torch.cuda.Stream(device=self.device)
         self.ticks = 0
         self.batch_sizes = []
+        self._ws = {}       # per kind, one workspace reused by every tick (grown on demand)
+        self._kfa = None    # keyframe descriptors, built once
+        self._est = {}      # workspace estimate per (section, camera, kind)
+        self.host_s = 0.0   # building plans and launching, per tick, summed
+        self.wait_s = 0.0   # waiting for the device after launching
 
     # -- admission ---------------------------------------------------------
     def _view_for(self, req):
@@ -83,21 +88,31 @@ class Server:
             v.with_pose_adam()
         return v
 
+    def _kf_array(self):
+        if self._kfa is None:
+            self._kfa = R.keyframe_array(self.keyframes)
+        return self._kfa
+
     def estimate_bytes(self, req):
         """Workspace of a one-view plan for this request (host-only sizing)
-        plus its output/observation buffers."""
+        plus its output/observation buffers; cached per section, camera and
+        kind."""
+        key = (req.section, tuple(req.cam), req.kind)
+        if key in self._est:
+            return self._est[key]
         L = _lib.load()
         first, count = self.sections[req.section]
-        kfs = self.keyframes
-        ka = (_lib.vtgs_keyframe * len(kfs))(*[k.cstruct() for k in kfs])
+        ka = self._kf_array()
         cam = R.Camera.of(req.cam)
         va = (_lib.vtgs_view * 1)(_lib.vtgs_view(cam.cstruct(), 1, first, count, None, None, None, None))
         import ctypes as C
         h = C.c_void_p()
-        _lib.check(L.vtgs_plan_create(ka, len(kfs), va, 1, C.byref(self.prm), 0, C.byref(h)))
+        _lib.check(L.vtgs_plan_create(ka, len(self.keyframes), va, 1, C.byref(self.prm), 0,
+                                      C.byref(h)))
         b = int(L.vtgs_plan_workspace_bytes(h))
         L.vtgs_plan_destroy(h)
-        return b + 5 * 4 * cam.P
+        self._est[key] = b + 5 * 4 * cam.P
+        return self._est[key]
 
     def submit(self, req):
         req.ws_bytes = self.estimate_bytes(req)
@@ -115,6 +130,14 @@ class Server:
             self.mem_used += req.ws_bytes
             self.peak_mem = max(self.peak_mem, self.mem_used)
             self.active.append(req)
+
+    def _plan(self, kind, views):
+        """A plan over this tick's views in the kind's reused workspace (the
+        previous tick on that stream has finished: ticks wait for both)."""
+        plan = R.Plan(self.keyframes, views, self.prm, device=self.device,
+                      workspace=self._ws.get(kind), kf_array=self._kf_array())
+        self._ws[kind] = plan.ws
+        return plan
 
     # -- one tick ----------------------------------------------------------
     def tick(self, now_fn=time.perf_counter):
@@ -141,14 +164,14 @@ class Server:
     def _execute(self, rend, trk):
         """One batched forward over the render requests and one tracking
         iteration over the track requests, on two streams; waits for both."""
+        t0 = time.perf_counter()
         main = torch.cuda.current_stream(self.device)
         ev = []
         out = plan_r = plan_t = loss = None
         if rend:
             self.s_render.wait_stream(main)
             with torch.cuda.stream(self.s_render):
-                plan_r = R.Plan(self.keyframes, [r._view for r in rend], self.prm,
-                                device=self.device)
+                plan_r = self._plan("render", [r._view for r in rend])
                 out = plan_r.render_fwd()
                 e = torch.cuda.Event()
                 e.record(self.s_render)
@@ -156,14 +179,16 @@ class Server:
         if trk:
             self.s_track.wait_stream(main)
             with torch.cuda.stream(self.s_track):
-                plan_t = R.Plan(self.keyframes, [r._view for r in trk], self.prm,
-                                device=self.device)
+                plan_t = self._plan("track", [r._view for r in trk])
                 loss = plan_t.track_step(self.cfg, 1)
                 e = torch.cuda.Event()
                 e.record(self.s_track)
                 ev.append(e)
+        t1 = time.perf_counter()
         for e in ev:
             e.synchronize()
+        self.host_s += t1 - t0
+        self.wait_s += time.perf_counter() - t1
         if rend:
             rc, need = plan_r.status(clear=True, stream=self.s_render)
             if rc != 0:
@@ -222,7 +247,7 @@ class Server:
                     p50_ms=pct(lat, 50), p99_ms=pct(lat, 99),
                     render_p50_ms=pct(rl, 50), render_p99_ms=pct(rl, 99),
                     track_p50_ms=pct(tl, 50), track_p99_ms=pct(tl, 99),
-                    ticks=self.ticks,
+                    ticks=self.ticks, host_s=self.host_s, device_wait_s=self.wait_s,
                     mean_batch=[float(np.mean([b[0] for b in self.batch_sizes])) if self.batch_sizes else 0,
                                 float(np.mean([b[1] for b in self.batch_sizes])) if self.batch_sizes else 0])
 

@@ -92,12 +92,33 @@ __device__ void se3_exp(const float *xi, float *E) {
   }
 }
 
-__global__ __launch_bounds__(kNT) void k_track_update(Ws ws, vtgs_track_cfg cfg, float *loss) {
-  __shared__ float lds[kNT / kWave];
+constexpr int kUpdNT = 1024;
+
+__global__ __launch_bounds__(kUpdNT) void k_track_update(Ws ws, vtgs_track_cfg cfg, float *loss) {
+  // the view's tile partials (6 twist sums + loss, stride 8): per thread,
+  // then per wave (DPP), then the 16 waves in order -- one barrier
+  __shared__ float part[kUpdNT / kWave][7];
   const int v = blockIdx.x;
-  float g[6], L;
-  reduce_view(ws, v, g, &L, lds);
+  const DevView &vw0 = ws.views[v];
+  float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int i = threadIdx.x; i < vw0.n_tiles; i += kUpdNT) {
+    const float *tp = ws.twist_part + 8 * (int64_t)(vw0.tile_base + i);
+#pragma unroll
+    for (int c = 0; c < 7; c++) acc[c] += tp[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 7; c++) {
+    const float sw = wave_sum(acc[c]);
+    if (lane_id() == 0) part[threadIdx.x / kWave][c] = sw;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  float g[6], L = 0.f;
+  for (int c = 0; c < 6; c++) g[c] = 0.f;
+  for (int w = 0; w < kUpdNT / kWave; w++) {
+    for (int c = 0; c < 6; c++) g[c] += part[w][c];
+    L += part[w][6];
+  }
   const DevView &vw = ws.views[v];
   if (loss) loss[(int64_t)(*ws.iter) * ws.n_views + v] = L;
   bool finite = __builtin_isfinite(L);
@@ -368,7 +389,7 @@ hipError_t launch_twist_reduce(const Ws &ws, float *g_twist, hipStream_t st) {
 
 hipError_t launch_track_update(const Ws &ws, const vtgs_track_cfg &cfg, float *loss,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_track_update, dim3(ws.n_views), dim3(kNT), 0, st, ws, cfg, loss);
+  hipLaunchKernelGGL(k_track_update, dim3(ws.n_views), dim3(kUpdNT), 0, st, ws, cfg, loss);
   return hipGetLastError();
 }
 

@@ -73,20 +73,21 @@ def flops_per_pair():
     return dict(fwd_contrib=25, bwd_contrib=99)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "composite_bwd_tracking_640x480_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "%s_tracking_640x480_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2506_02741_amd", "csrc", f)
                    for f in ("k_composite.hip", "vtgs_internal.h")]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the tracking backward from the committed
-    counter summary, or None when the kernel sources changed since the
-    counters were taken (the summary records their SHA-256)."""
+def measured_traffic(stage="composite_bwd"):
+    """HBM bytes per launch of a tracking compositing kernel from the
+    committed counter summary, or None when the kernel sources changed since
+    the counters were taken (the summary records their SHA-256)."""
     import hashlib
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILE % stage if "%s" in TRAFFIC_FILE else TRAFFIC_FILE
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
@@ -438,12 +439,16 @@ def main():
         achieved = work / (avg[dom] * 1e-3) / 1e12
         roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS,
-                    traffic=measured_traffic() if dom == "composite_bwd" else None,
+                    traffic=measured_traffic(dom),
                     avg_ms=avg[dom], flops_per_launch=work,
                     units="%d contributing (pixel, Gaussian) pairs x %d FLOP" % (contrib, per))
-        fw = avg.get("composite_fwd")
-        if fw:
-            roof["composite_fwd"] = dict(avg_ms=fw, achieved=contrib * fl["fwd_contrib"] / (fw * 1e-3) / 1e12)
+        # the other compositing kernel, same accounting
+        other = "composite_bwd" if dom == "composite_fwd" else "composite_fwd"
+        if avg.get(other):
+            op = fl["bwd_contrib"] if other == "composite_bwd" else fl["fwd_contrib"]
+            a2 = contrib * op / (avg[other] * 1e-3) / 1e12
+            roof[other] = dict(avg_ms=avg[other], achieved=a2, frac=a2 / PEAK_FP32_TFLOPS,
+                               traffic=measured_traffic(other))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -147,6 +147,6 @@ def test_bench_traffic_summary_tracks_kernel_sources(tmp_path, monkeypatch):
     f.write_text("hbm_bytes_per_launch: 1234\nsources_sha256: %s\n" % good)
     monkeypatch.setattr(b, "TRAFFIC_FILE", str(f))
     monkeypatch.setattr(b, "TRAFFIC_SOURCES", [str(src)])
-    assert b.measured_traffic() == 1234.0
+    assert b.measured_traffic("composite_bwd") == 1234.0
     src.write_bytes(b"kernel source, changed")
-    assert b.measured_traffic() is None
+    assert b.measured_traffic("composite_bwd") is None

@@ -7,7 +7,10 @@
 // while staging, the block marks for every wave which entries have an
 // extent box that touches the wave's pixels (one 64-bit mask per wave and
 // 64 entries), and each wave then visits only the set bits of its masks
-// with scalar bit scans, two entries per step.
+// with scalar bit scans, two entries per step, recording for each lane which
+// entries reach its pixel.  The lanes then composite their own entries of a
+// group of chunks (up to 256 entries) as one stream each, so a wave takes as
+// many steps as its busiest lane has entries in the whole group.
 //
 // Forward, per pixel, front to back [splat of Sec. 3.3]:
 //   q = d^T Q d with d = pixel - mu; skip q > q_cut
@@ -137,6 +140,34 @@ __device__ __forceinline__ float quad2(const float4 &e0, float qc, float px, flo
   return q;
 }
 
+// Chunks of 64 entries whose lane bits one phase-2 pass walks as a single
+// stream per lane (a lane then steps once per entry that reaches its pixel,
+// not once per entry of the busiest lane of every chunk).  Four pixels per
+// lane keep one chunk per pass to bound the LDS word lists.
+template <int TILE, int BATCH>
+struct Group {
+  static constexpr int NCB = BATCH / kWave;  // chunks of a full batch
+  static constexpr int G = Shape<TILE>::PPT > 1 ? 1 : (NCB < 4 ? NCB : 4);
+  static constexpr int NS = 2 * G + 2;       // LDS word slots per pixel
+};
+
+// Word list of one pixel-lane: the nonzero 32-entry halves of its bits in
+// slots 0.., a zero word after the last; `seq` holds each slot's half index
+// within the group, four bits per slot, the current slot's in bits 0-3.
+template <int NS, int NR>
+__device__ __forceinline__ void push_word(uint32_t (*words)[NR][kWave], int row, uint32_t word,
+                                          uint32_t half, uint32_t &ns, uint32_t &seq) {
+  if (word != 0u) {
+    words[ns][row][lane_id()] = word;
+    seq |= half << (4u * ns);
+    ns++;
+  }
+}
+
+// Lowest set bit of a word, 31 for a zero word (an index that stays inside
+// the group, read and then ignored).
+__device__ __forceinline__ int low_bit(uint32_t v) { return __builtin_ctz(v | 0x80000000u); }
+
 // Gather entry `id` of the view's records (an id out of range, which a
 // consistent list never holds, yields an entry that every wave skips).
 __device__ __forceinline__ void load_entry(const Ws &ws, const DevView &vw, uint32_t id,
@@ -158,8 +189,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
   constexpr int NW = NT / kWave;
   constexpr int PER = (BATCH + NT - 1) / NT;  // list entries each thread stages per batch
   constexpr int NCH = PER * NT / kWave;       // 64-entry chunks of a staged batch
+  constexpr int G = Group<TILE, BATCH>::G, NS = Group<TILE, BATCH>::NS, NR = NW * PPT;
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
   __shared__ unsigned long long masks[NW][NCH];
+  __shared__ uint32_t words[NS][NR][kWave];
   const int t = blockIdx.x;
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
   const int lt = t - vw.tile_base;
@@ -225,69 +258,88 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
     }
     if (wave_done()) continue;
     const uint32_t base = (uint32_t)(b - start + 1);
-    for (int c = 0; c * kWave < nb; c++) {
-      unsigned long long m = uniform_u64(masks[w][c]);
-      if (m == 0ull) continue;
-      // 1. which of the chunk's entries reach each of this lane's pixels
-      // bits 0-31 and 32-63 of the chunk in two words; entry j is uniform,
-      // so the half it lands in is a scalar choice
-      uint32_t own_lo[PPT], own_hi[PPT];
+    const int nch = (nb + kWave - 1) / kWave;
+    for (int g0 = 0; g0 < nch; g0 += G) {
+      uint32_t ns[PPT], seq[PPT];
 #pragma unroll
-      for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
-      for (int h = 0; h < 2; h++) {
-        uint32_t mh = (uint32_t)(m >> (32 * h));
-        while (mh) {  // two entries per step, both loads issued first
-          const int ja = __builtin_ctz(mh);
-          mh &= mh - 1u;
-          const bool hb = mh != 0u;
-          const int jb = hb ? __builtin_ctz(mh) : ja;
-          mh &= hb ? mh - 1u : mh;
-          const int ia = c * kWave + 32 * h + ja, ib = c * kWave + 32 * h + jb;
-          const float4 a0 = e0s[ia], b0 = e0s[ib];
-          const float aq = e1s[ia].x, bq = e1s[ib].x;
+      for (int k = 0; k < PPT; k++) ns[k] = seq[k] = 0u;
+      const int cend = min(g0 + G, nch);
+      for (int c = g0; c < cend; c++) {
+        const unsigned long long m = uniform_u64(masks[w][c]);
+        if (m == 0ull) continue;
+        // 1. which of the chunk's entries reach each of this lane's pixels
+        // bits 0-31 and 32-63 of the chunk in two words; entry j is uniform,
+        // so the half it lands in is a scalar choice
+        uint32_t own_lo[PPT], own_hi[PPT];
 #pragma unroll
-          for (int k = 0; k < PPT; k++) {
-            const float qa = quad2(a0, aq, px[k], py[k]);
-            const float qb = quad2(b0, bq, px[k], py[k]);
-            const uint32_t bits = ((!done[k] && qa <= qcut) ? (1u << ja) : 0u) |
-                                  ((!done[k] && qb <= qcut) ? (1u << jb) : 0u);
-            if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
+        for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
+        for (int h = 0; h < 2; h++) {
+          uint32_t mh = (uint32_t)(m >> (32 * h));
+          while (mh) {  // two entries per step, both loads issued first
+            const int ja = __builtin_ctz(mh);
+            mh &= mh - 1u;
+            const bool hb = mh != 0u;
+            const int jb = hb ? __builtin_ctz(mh) : ja;
+            mh &= hb ? mh - 1u : mh;
+            const int ia = c * kWave + 32 * h + ja, ib = c * kWave + 32 * h + jb;
+            const float4 a0 = e0s[ia], b0 = e0s[ib];
+            const float aq = e1s[ia].x, bq = e1s[ib].x;
+#pragma unroll
+            for (int k = 0; k < PPT; k++) {
+              const float qa = quad2(a0, aq, px[k], py[k]);
+              const float qb = quad2(b0, bq, px[k], py[k]);
+              const uint32_t bits = ((!done[k] && qa <= qcut) ? (1u << ja) : 0u) |
+                                    ((!done[k] && qb <= qcut) ? (1u << jb) : 0u);
+              if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
+            }
           }
         }
-      }
-      unsigned long long own[PPT];
+        {
+          // kept for the backward, which replays the same chunks
+          unsigned long long *dst = ws.lane_bits + chunk_word(start, b - start, c, t, w, NW, PPT);
 #pragma unroll
-      for (int k = 0; k < PPT; k++) own[k] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
-      {
-        // kept for the backward, which replays the same chunks
-        unsigned long long *dst = ws.lane_bits + chunk_word(start, b - start, c, t, w, NW, PPT);
+          for (int k = 0; k < PPT; k++)
+            dst[k * kWave + lane_id()] = ((unsigned long long)own_hi[k] << 32) | own_lo[k];
+        }
 #pragma unroll
-        for (int k = 0; k < PPT; k++) dst[k * kWave + lane_id()] = own[k];
+        for (int k = 0; k < PPT; k++) {
+          const uint32_t hh = 2u * (uint32_t)(c - g0);
+          push_word<NS, NR>(words, w * PPT + k, own_lo[k], hh, ns[k], seq[k]);
+          push_word<NS, NR>(words, w * PPT + k, own_hi[k], hh + 1u, ns[k], seq[k]);
+        }
       }
-      // 2. each lane composites its own entries in list order
+      // 2. each lane composites its own entries of the group in list order,
+      // one step per entry; the wave runs until its last lane is through
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
-        unsigned long long bits = own[k];
-        const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        const int row = w * PPT + k;
+        words[ns[k]][row][lane_id()] = 0u;
+        uint32_t cur = words[0][row][lane_id()], nxt = words[1][row][lane_id()];
+        uint32_t sq = seq[k], sp = 0u;
+        const int gb = g0 * kWave;
         // the next entry's LDS reads are issued before this one is composited
-        int i = c * kWave + (bits != 0ull ? __builtin_ctzll(bits) : 0);
+        int i = gb + (int)((sq & 15u) << 5) + low_bit(cur);
         float4 n0 = e0s[i], n1 = e1s[i], n2 = e2s[i];
-        for (int n = 0; n < steps; n++) {
-          const bool have = bits != 0ull;
-          bits &= bits - 1ull;
+        while (cur != 0u) {
           const float4 e0 = n0, e1 = n1, e2 = n2;
           const uint32_t pos = base + (uint32_t)i;
-          i = c * kWave + (bits != 0ull ? __builtin_ctzll(bits) : 0);
+          cur &= cur - 1u;
+          const bool z = cur == 0u;
+          cur = z ? nxt : cur;
+          sq = z ? sq >> 4 : sq;
+          sp += z ? 1u : 0u;
+          nxt = words[sp + 1u][row][lane_id()];
+          i = gb + (int)((sq & 15u) << 5) + low_bit(cur);
           n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i];
           const float q = quad2(e0, e1.x, px[k], py[k]);
-          const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-          const float a = fminf(amax, e1.y * G);
-          const bool ok = have && (a >= amin);
+          const float gau = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+          const float a = fminf(amax, e1.y * gau);
+          const bool ok = a >= amin;
           const float Tn = T[k] * (1.0f - a);
           const bool stop = ok && (Tn < tmin);
           const bool take = ok && !stop;
           done[k] = done[k] || stop;
-          bits = stop ? 0ull : bits;
+          cur = stop ? 0u : cur;
           const float wgt = take ? a * T[k] : 0.f;
           C0[k] = fmaf(e2.x, wgt, C0[k]);
           C1[k] = fmaf(e2.y, wgt, C1[k]);
@@ -359,6 +411,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   constexpr int NCH = PER * NT / kWave;
   constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
   constexpr int AB = kSlots ? BATCH : 1;
+  constexpr int G = Group<TILE, BATCH>::G, NS = Group<TILE, BATCH>::NS, NR = NW * PPT;
   // staged entry: e0 (mx, my, qa, 2 qb), e1 (qc, o, z, qb), e2 (c, r)
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
   __shared__ float4 ejs[BATCH];   // (fx/z, fy/z, -fx px/z^2, -fy py/z^2)
@@ -368,6 +421,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   __shared__ int maxlast_s;
   __shared__ float red_s[NW][7];
   __shared__ unsigned long long masks[NW][NCH];
+  __shared__ uint32_t words[NS][NR][kWave];
 
   const int t = blockIdx.x;
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
@@ -488,15 +542,20 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
     }
     // this wave's entries, last to first, below its own last contributor
     const int lim = min(nb, wstop - lo);
-    for (int c = (lim - 1) / kWave; lim > 0 && c >= 0; c--) {
-      unsigned long long m = uniform_u64(masks[w][c]);
-      const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
-      if (top < kWave) m &= (1ull << top) - 1ull;
-      if (m == 0ull) continue;
-      // 1. the entries of this chunk that reached each of this lane's pixels
-      // in the forward, cut at the pixel's last contributor
-      unsigned long long own[PPT];
-      {
+    const int ctop = (lim - 1) / kWave;
+    for (int g0 = (ctop / G) * G; lim > 0 && g0 >= 0; g0 -= G) {
+      // 1. the entries of the group's chunks that reached each of this lane's
+      // pixels in the forward, cut at the pixel's last contributor; the words
+      // go in bit-reversed, top half first, so the lowest set bit of a word is
+      // the lane's next entry towards the front
+      uint32_t ns[PPT], seq[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; k++) ns[k] = seq[k] = 0u;
+      for (int c = min(g0 + G - 1, ctop); c >= g0; c--) {
+        unsigned long long m = uniform_u64(masks[w][c]);
+        const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
+        if (top < kWave) m &= (1ull << top) - 1ull;
+        if (m == 0ull) continue;
         const unsigned long long *src =
             ws.lane_bits + chunk_word(start, lo - start, c, t, w, NW, PPT);
         const int base = lo - start + c * kWave;
@@ -505,32 +564,43 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const int lim_k = (int)last[k] - base;
           const unsigned long long below =
               lim_k >= kWave ? ~0ull : (lim_k <= 0 ? 0ull : (1ull << lim_k) - 1ull);
-          own[k] = src[k * kWave + lane_id()] & below & m;
+          const unsigned long long own = src[k * kWave + lane_id()] & below & m;
+          const uint32_t hh = 2u * (uint32_t)(c - g0);
+          push_word<NS, NR>(words, w * PPT + k, __builtin_bitreverse32((uint32_t)(own >> 32)),
+                            hh + 1u, ns[k], seq[k]);
+          push_word<NS, NR>(words, w * PPT + k, __builtin_bitreverse32((uint32_t)own), hh,
+                            ns[k], seq[k]);
         }
       }
-      // 2. each lane replays its own entries, last to first
+      // 2. each lane replays its own entries of the group, last to first, one
+      // step per entry; the wave runs until its last lane is through
 #pragma unroll
       for (int k = 0; k < PPT; k++) {
-        unsigned long long bits = own[k];
-        const int steps = __builtin_amdgcn_readfirstlane(wave_max_i(__popcll(bits)));
+        const int row = w * PPT + k;
+        words[ns[k]][row][lane_id()] = 0u;
+        uint32_t cur = words[0][row][lane_id()], nxt = words[1][row][lane_id()];
+        uint32_t sq = seq[k], sp = 0u;
+        const int gb = g0 * kWave + 31;
         // the next entry's LDS reads are issued before this one is replayed
-        int jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
-        float4 n0 = e0s[c * kWave + jj], n1 = e1s[c * kWave + jj], n2 = e2s[c * kWave + jj];
-        float4 nj = ejs[c * kWave + jj], np = eps_[c * kWave + jj];
-        for (int n = 0; n < steps; n++) {
-          const bool have = bits != 0ull;
-          bits &= have ? ~(1ull << jj) : ~0ull;
+        int i = gb + (int)((sq & 15u) << 5) - low_bit(cur);
+        float4 n0 = e0s[i], n1 = e1s[i], n2 = e2s[i], nj = ejs[i], np = eps_[i];
+        while (cur != 0u) {
           const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
-          const int cur = c * kWave + jj;  // this entry's batch position
-          jj = bits != 0ull ? 63 - __builtin_clzll(bits) : 0;
-          const int nxt = c * kWave + jj;
-          n0 = e0s[nxt]; n1 = e1s[nxt]; n2 = e2s[nxt]; nj = ejs[nxt]; np = eps_[nxt];
+          const int cur_i = i;  // this entry's batch position
+          cur &= cur - 1u;
+          const bool z = cur == 0u;
+          cur = z ? nxt : cur;
+          sq = z ? sq >> 4 : sq;
+          sp += z ? 1u : 0u;
+          nxt = words[sp + 1u][row][lane_id()];
+          i = gb + (int)((sq & 15u) << 5) - low_bit(cur);
+          n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i]; nj = ejs[i]; np = eps_[i];
           const float dx = px[k] - e0.x, dy = py[k] - e0.y;
           const float q = quad2(e0, e1.x, px[k], py[k]);
-          const float G = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
-          const float a = fminf(amax, e1.y * G);
-          const bool ok = have && (a >= amin);
-          const float oG = e1.y * G;
+          const float gau = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
+          const float a = fminf(amax, e1.y * gau);
+          const bool ok = a >= amin;
+          const float oG = e1.y * gau;
           const float om = 1.0f - a;
           const float Tk = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
           T[k] = Tk;
@@ -547,24 +617,24 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
           if (kTwist) {
             const float kk = ep.z;
-            const float g0 = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
-            const float g1 = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
+            const float g0v = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
+            const float g1v = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
             const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
-            const float g2 = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+            const float g2v = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
             const float pz = e1.z;
-            tw[0] += g0; tw[1] += g1; tw[2] += g2;
-            tw[3] += ep.y * g2 - pz * g1;
-            tw[4] += pz * g0 - ep.x * g2;
-            tw[5] += ep.x * g1 - ep.y * g0;
+            tw[0] += g0v; tw[1] += g1v; tw[2] += g2v;
+            tw[3] += ep.y * g2v - pz * g1v;
+            tw[4] += pz * g0v - ep.x * g2v;
+            tw[5] += ep.x * g1v - ep.y * g0v;
           }
           if (kSlots && ok && ep.w != 0.f) {
             // this wave's accumulators: only its own lanes add to them
             const float tt = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
-            atomicAdd(&acc[w][0][cur], wgt * gC0[k]);
-            atomicAdd(&acc[w][1][cur], wgt * gC1[k]);
-            atomicAdd(&acc[w][2][cur], wgt * gC2[k]);
-            atomicAdd(&acc[w][3][cur], pass ? G * dLda : 0.f);
-            atomicAdd(&acc[w][4][cur], dLdq * (-2.0f * e2.w * tt));
+            atomicAdd(&acc[w][0][cur_i], wgt * gC0[k]);
+            atomicAdd(&acc[w][1][cur_i], wgt * gC1[k]);
+            atomicAdd(&acc[w][2][cur_i], wgt * gC2[k]);
+            atomicAdd(&acc[w][3][cur_i], pass ? gau * dLda : 0.f);
+            atomicAdd(&acc[w][4][cur_i], dLdq * (-2.0f * e2.w * tt));
           }
         }
       }

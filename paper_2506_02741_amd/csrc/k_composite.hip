@@ -83,14 +83,28 @@ __device__ __forceinline__ void block_of(int ww, int &x0, int &y0) {
   y0 = (ww / 2) * Shape<TILE>::WB;
 }
 
+// Squared radius of a circle around mu that holds every offset d with
+// d^T Q d <= q_cut: |d|^2 <= q_cut / lambda_min(Q) = q_cut lambda_max / det,
+// widened by 2 % so that the FP32 value of q can never pass the cut outside
+// it.  A conic that is not positive definite gets no circle (box test only).
+__device__ __forceinline__ float cull_r2(float qa, float qb, float qc, float qcut) {
+  const float h = 0.5f * (qa - qc);
+  const float lmax = 0.5f * (qa + qc) + sqrtf(fmaf(h, h, qb * qb));
+  const float det = fmaf(qa, qc, -qb * qb);
+  return det > 0.f ? 1.0201f * qcut * lmax / det : 3.0e38f;
+}
+
 // Wave masks of a staged batch: bit (i % 64) of masks[ww][i / 64] is set
-// when entry i is present and its extent box mu +- R touches wave ww's
-// pixel block.  Called by every lane (the ballot is wave-wide); the lanes of
-// a wave stage 64 consecutive entries, so i / 64 is uniform.
+// when entry i is present and reaches wave ww's pixel block: its extent box
+// mu +- R touches the block and the block lies within the cull circle.
+// Called by every lane (the ballot is wave-wide); the lanes of a wave stage
+// 64 consecutive entries, so i / 64 is uniform.
 template <int TILE, int NCH>
 __device__ __forceinline__ void stage_masks(unsigned long long (*masks)[NCH], int i, bool have,
-                                            const float4 &e0, float R, float ox, float oy) {
+                                            const float4 &e0, float qc, float R, float qcut,
+                                            float ox, float oy) {
   constexpr int NW = Shape<TILE>::NT / kWave, WB = Shape<TILE>::WB;
+  const float r2 = cull_r2(e0.z, e0.w, qc, qcut);
 #pragma unroll
   for (int ww = 0; ww < NW; ww++) {
     int x0, y0;
@@ -98,7 +112,11 @@ __device__ __forceinline__ void stage_masks(unsigned long long (*masks)[NCH], in
     const float bx0 = ox + (float)x0, by0 = oy + (float)y0;
     const float bx1 = bx0 + (float)(WB - 1), by1 = by0 + (float)(WB - 1);
     const bool miss = (e0.x + R < bx0) | (e0.x - R > bx1) | (e0.y + R < by0) | (e0.y - R > by1);
-    const unsigned long long m = ballot64(have && !miss);
+    // distance from mu to the nearest pixel centre of the block
+    const float gx = fmaxf(fmaxf(bx0 - e0.x, e0.x - bx1), 0.f);
+    const float gy = fmaxf(fmaxf(by0 - e0.y, e0.y - by1), 0.f);
+    const bool far = fmaf(gx, gx, gy * gy) > r2;
+    const unsigned long long m = ballot64(have && !miss && !far);
     if (lane_id() == 0) masks[ww][i / kWave] = m;
   }
 }
@@ -247,7 +265,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
         e0s[i] = make_float4(p0[k].x, p0[k].y, p0[k].z, 2.0f * p0[k].w);
         e1s[i] = p1[k]; e2s[i] = p2[k];
       }
-      stage_masks<TILE, NCH>(masks, i, have, p0[k], p1[k].w, (float)ox, (float)oy);
+      stage_masks<TILE, NCH>(masks, i, have, p0[k], p1[k].x, p1[k].w, qcut, (float)ox, (float)oy);
     }
     __syncthreads();
     const int nx = b + BATCH;
@@ -512,7 +530,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
-      stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.w, (float)ox, (float)oy);
+      stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.x, st[k].e1.w, qcut, (float)ox,
+                             (float)oy);
       if (i >= nb) continue;
       const BwdEntry &E = st[k];
       // the doubled off-diagonal conic term (exact) for q, the plain one

@@ -461,6 +461,168 @@ __device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long 
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// One-wave tile sort (lists of up to 15 keys per lane)
+// ---------------------------------------------------------------------------
+// LDS slot of list position i: one spare slot after every 16, so that the
+// lanes reading positions t*E .. t*E+E-1 spread over the banks.
+__device__ __forceinline__ int lds_pos(int i) { return i + (i >> 4); }
+
+// Wave OR / AND of a uint32 (all 64 lanes active), uniform result.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xf, 0xf, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xf, 0xf, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x122, 0xf, 0xf, false);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x121, 0xf, 0xf, false);
+  return ((uint32_t)__builtin_amdgcn_readlane((int)x, 0) | (uint32_t)__builtin_amdgcn_readlane((int)x, 16)) |
+         ((uint32_t)__builtin_amdgcn_readlane((int)x, 32) | (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+}
+__device__ __forceinline__ uint32_t wave_and_u32(uint32_t x) {
+  x &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x128, 0xf, 0xf, false);
+  x &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x124, 0xf, 0xf, false);
+  x &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x122, 0xf, 0xf, false);
+  x &= (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)x, 0x121, 0xf, 0xf, false);
+  return ((uint32_t)__builtin_amdgcn_readlane((int)x, 0) & (uint32_t)__builtin_amdgcn_readlane((int)x, 16)) &
+         ((uint32_t)__builtin_amdgcn_readlane((int)x, 32) & (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+}
+
+// Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
+// of the 64 * E keys of a one-wave block, lane t holding keys t*E ..
+// t*E+E-1.  Per pass each lane counts its keys per digit in the 4-bit fields
+// of one u64 (E <= 15), a DPP scan of the counts (as 16-bit fields) and the
+// wave totals give the lane's start in every digit bucket, which the lane
+// parks in LDS so that each key fetches its own; the keys are scattered in
+// lane-then-register order, which keeps each pass stable.  On return the
+// registers and buf (at lds_pos) hold the keys in the new order.
+template <int E>
+__device__ __forceinline__ void wave_radix_passes(unsigned long long (&k)[E], unsigned long long digits,
+                                  unsigned long long *buf, uint32_t *starts) {
+  static_assert(E <= 15, "4-bit digit counters");
+  const int l = lane_id();
+  for (int sh = 0; sh < 64; sh += 4) {
+    if (((digits >> sh) & 15ull) == 0ull) continue;
+    int dg[E];
+    unsigned long long cnt = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = (int)((k[e] >> sh) & 15ull);
+      dg[e] = d;
+      cnt += 1ull << (4 * d);
+    }
+    const uint32_t clo = (uint32_t)cnt, chi = (uint32_t)(cnt >> 32);
+    uint32_t run = 0u;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      // digits 2q and 2q + 1 as 16-bit fields, scanned over the wave
+      const uint32_t v = q < 4 ? clo : chi;
+      const int o = 8 * (q & 3);
+      const uint32_t c = ((v >> o) & 15u) | (((v >> (o + 4)) & 15u) << 16);
+      const uint32_t inc = wave_incl_scan_u32(c);
+      const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+      const uint32_t a = tot & 0xffffu;
+      starts[q * kWave + l] = inc - c + (run | ((run + a) << 16));
+      run += a + (tot >> 16);
+    }
+    unsigned long long seen = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = dg[e];
+      const uint32_t w = starts[(d >> 1) * kWave + l];
+      const uint32_t pos =
+          ((w >> (16 * (d & 1))) & 0xffffu) + (uint32_t)((seen >> (4 * d)) & 15ull);
+      seen += 1ull << (4 * d);
+      buf[lds_pos((int)min(pos, (uint32_t)(kWave * E - 1)))] = k[e];  // a permutation
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; e++) k[e] = buf[lds_pos(l * E + e)];
+    __syncthreads();
+  }
+}
+
+// Sort of one tile's n <= 64 * E keys (depth bits << 32 | id, unique) by a
+// one-wave block; the ids go to dst in ascending key order.  The keys are
+// loaded coalesced (any starting arrangement sorts to the same result, the
+// keys being unique).  Depth first, over the depth nibbles that vary; equal
+// depths (rare) are then put in id order as in the block sort.
+template <int E>
+__device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, uint32_t *dst, int n,
+                               unsigned long long *buf, uint32_t *starts) {
+  const int l = lane_id();
+  unsigned long long k[E];
+  uint32_t olo = 0u, ohi = 0u, alo = ~0u, ahi = ~0u;
+  // every load first (clamped index), then the padding: no wait per load
+#pragma unroll
+  for (int e = 0; e < E; e++) k[e] = src[min(l + kWave * e, n - 1)];
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const bool in = l + kWave * e < n;
+    k[e] = in ? k[e] : ~0ull;
+    olo |= in ? (uint32_t)k[e] : 0u;
+    ohi |= in ? (uint32_t)(k[e] >> 32) : 0u;
+    alo &= in ? (uint32_t)k[e] : ~0u;
+    ahi &= in ? (uint32_t)(k[e] >> 32) : ~0u;
+  }
+  const unsigned long long diff =
+      ((unsigned long long)(wave_or_u32(ohi) ^ wave_and_u32(ahi)) << 32) |
+      (wave_or_u32(olo) ^ wave_and_u32(alo));
+  if ((diff >> 32) == 0ull) {
+    // one depth for the whole tile: the order is the id order
+#pragma unroll
+    for (int e = 0; e < E; e++) buf[lds_pos(l * E + e)] = k[e];
+    wave_radix_passes<E>(k, diff & 0xFFFFFFFFull, buf, starts);
+  } else {
+    wave_radix_passes<E>(k, diff & 0xFFFFFFFF00000000ull, buf, starts);
+    // equal depths at consecutive positions?
+    const uint32_t nxt = (uint32_t)__shfl_down((int)(uint32_t)(k[0] >> 32), 1);
+    bool tie = false;
+#pragma unroll
+    for (int e = 0; e + 1 < E; e++)
+      tie |= l * E + e + 1 < n && (uint32_t)(k[e] >> 32) == (uint32_t)(k[e + 1] >> 32);
+    tie |= l + 1 < kWave && l * E + E < n && (uint32_t)(k[E - 1] >> 32) == nxt;
+    if (ballot64(tie) != 0ull) {
+      // runs of equal depth: each put in id order by the lane holding its
+      // first key (insertion sort), unless one is longer than 64, in which
+      // case every varying nibble (id, then depth) is sorted by radix
+      bool long_run = false;
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        const int i = l * E + e;
+        if (i + 1 >= n) continue;
+        const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
+        if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
+            (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
+        int len = 2;
+        while (i + len < n && len <= 64 && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
+        long_run = long_run || len > 64;
+      }
+      if (ballot64(long_run) != 0ull) {
+        wave_radix_passes<E>(k, diff & 0x00000000FFFFFFFFull, buf, starts);
+        wave_radix_passes<E>(k, diff & 0xFFFFFFFF00000000ull, buf, starts);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+          const int i = l * E + e;
+          if (i + 1 >= n) continue;
+          const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
+          if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
+              (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
+          int len = 2;
+          while (i + len < n && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
+          for (int a = i + 1; a < i + len; a++) {
+            const unsigned long long v = buf[lds_pos(a)];
+            int b = a - 1;
+            while (b >= i && buf[lds_pos(b)] > v) { buf[lds_pos(b + 1)] = buf[lds_pos(b)]; b--; }
+            buf[lds_pos(b + 1)] = v;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  for (int i = l; i < n; i += kWave) dst[i] = (uint32_t)buf[lds_pos(i)];
+}
+
 // Bitonic sort with ascending comparators only (a flip stage then
 // half-cleaners), so indices >= n behave as +infinity and need no padding.
 // Used in global memory for tiles longer than the LDS capacity.
@@ -493,13 +655,34 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
   }
 }
 
+// Sort of one tile's n keys with EE keys per thread (n <= NT * EE), the ids
+// written to dst in ascending key order.
+template <int NT, int EE>
+__device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, uint32_t *dst, int n,
+                                               unsigned long long *buf, uint32_t (*wsum)[8],
+                                               unsigned long long *red) {
+  unsigned long long k[EE];
+  // every load first (clamped index), then the padding: no wait per load
+#pragma unroll
+  for (int e = 0; e < EE; e++) k[e] = src[min((int)threadIdx.x * EE + e, n - 1)];
+#pragma unroll
+  for (int e = 0; e < EE; e++) k[e] = (int)threadIdx.x * EE + e < n ? k[e] : ~0ull;
+  block_sort_u64<NT, EE>(k, n, buf, wsum, red);
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
+}
+
 // One block per tile: keys (depth bits << 32 | id) are unique within a tile,
 // so ascending key order is the (depth, id) order.  Each variant handles the
-// tiles whose length lies in (lo_n, hi_n]; longer than NT * E -> global memory.
+// tiles whose length lies in (lo_n, hi_n]; a list is held in registers with
+// the fewest keys per thread that fit it (E / 8, E / 4 + E / 8 or E), and
+// longer than NT * E -> global memory.
 template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, int queued) {
   constexpr int CAP = NT * E;
-  __shared__ unsigned long long buf[CAP];
+  constexpr int E1 = E / 8, E2 = E / 4 + E / 8;
+  constexpr bool kWaveSort = NT == kWave && E2 <= 15;
+  __shared__ unsigned long long buf[CAP + (kWaveSort ? CAP / 16 : 0)];
+  __shared__ uint32_t starts[kWaveSort ? 8 * kWave : 1];
   __shared__ uint32_t wsum[NT / kWave][8];
   __shared__ unsigned long long red[2 * (NT / kWave)];
   // short lists: tile = block; long lists: blocks take queued tiles in turn
@@ -531,25 +714,16 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, in
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
     continue;
   }
-  if (n <= CAP / 2) {
-    // half the registers per thread when half the capacity suffices
-    unsigned long long k[E / 2];
-#pragma unroll
-    for (int e = 0; e < E / 2; e++) {
-      const int i = threadIdx.x * (E / 2) + e;
-      k[e] = i < n ? src[i] : ~0ull;
-    }
-    block_sort_u64<NT, E / 2>(k, n, buf, wsum, red);
-    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
+  if (kWaveSort && n <= NT * E1) {
+    wave_sort_tile<E1>(src, dst, n, buf, starts);
+  } else if (kWaveSort && n <= NT * E2) {
+    wave_sort_tile<E2>(src, dst, n, buf, starts);
+  } else if (n <= NT * E1) {
+    sort_tile_regs<NT, E1>(src, dst, n, buf, wsum, red);
+  } else if (n <= NT * E2) {
+    sort_tile_regs<NT, E2>(src, dst, n, buf, wsum, red);
   } else if (n <= CAP) {
-    unsigned long long k[E];
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-      const int i = threadIdx.x * E + e;
-      k[e] = i < n ? src[i] : ~0ull;
-    }
-    block_sort_u64<NT, E>(k, n, buf, wsum, red);
-    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
+    sort_tile_regs<NT, E>(src, dst, n, buf, wsum, red);
   } else {
     unsigned long long *g = ws.keys_tmp + rg.x;
     for (int i = threadIdx.x; i < n; i += NT) g[i] = src[i];
@@ -656,12 +830,19 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 }
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
-  hipLaunchKernelGGL((k_sort_tiles<256, kSmallSort / 256>), dim3(ws.n_tiles), dim3(256), 0, st,
-                     ws, 0, kSmallSort, 0);
-  // long lists, queued by the scan: two 512-thread blocks per CU take them
-  // in turn (most views have none, and the launch then ends at once)
-  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(std::min(ws.n_tiles, 512)), dim3(512),
-                     0, st, ws, kSmallSort, 0x7fffffff, 1);
+  // one wave per tile: 8, 12 or 32 keys per lane
+  hipLaunchKernelGGL((k_sort_tiles<kWave, kSmallSort / kWave>), dim3(ws.n_tiles), dim3(kWave), 0,
+                     st, ws, 0, kSmallSort, 0);
+  // long lists, queued by the scan, taken in turn by 512-thread blocks: two
+  // per CU when the records' expected pairs per tile (a Gaussian of extent
+  // ~4-5 px covers about (1 + 10 / B)^2 tiles of side B) make long lists the
+  // rule, else a few blocks for the odd one (an empty queue ends them at once,
+  // and a smaller grid ends sooner)
+  const double per = (1.0 + 10.0 / ws.tile) * (1.0 + 10.0 / ws.tile);
+  const bool many = per * (double)ws.n_rec > 0.5 * kSmallSort * (double)ws.n_tiles;
+  const int nlong = std::min(ws.n_tiles, many ? 512 : 16);
+  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(nlong), dim3(512), 0, st, ws,
+                     kSmallSort, 0x7fffffff, 1);
   return hipGetLastError();
 }
 

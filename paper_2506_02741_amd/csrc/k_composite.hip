@@ -186,18 +186,15 @@ __device__ __forceinline__ void push_word(uint32_t (*words)[NR][kWave], int row,
 // the group, read and then ignored).
 __device__ __forceinline__ int low_bit(uint32_t v) { return __builtin_ctz(v | 0x80000000u); }
 
-// Gather entry `id` of the view's records (an id out of range, which a
-// consistent list never holds, yields an entry that every wave skips).
-__device__ __forceinline__ void load_entry(const Ws &ws, const DevView &vw, uint32_t id,
-                                           float4 &e0, float4 &e1, float4 &e2) {
-  if (id < (uint32_t)vw.n_rec) {
-    const float4 *A = ws.recA + 3 * ((int64_t)vw.rec_base + id);
-    e0 = A[0]; e1 = A[1]; e2 = A[2];
-  } else {
-    e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
-    e1 = make_float4(0.f, 0.f, 1.f, 0.f);
-    e2 = make_float4(0.f, 0.f, 0.f, 0.f);
-  }
+// Gather the record of entry `id` of the view.  No branch around the loads
+// (so that nothing waits for them before their use): an id out of range,
+// which a consistent list never holds, reads record 0 and clears `ok`, and
+// the staging then leaves the entry out of every wave's mask.
+__device__ __forceinline__ void fetch_record(const Ws &ws, int n_rec, int rec_base, uint32_t id,
+                                             float4 &e0, float4 &e1, float4 &e2, bool &ok) {
+  ok = id < (uint32_t)n_rec;
+  const float4 *A = ws.recA + 3 * ((int64_t)rec_base + (ok ? id : 0u));
+  e0 = A[0]; e1 = A[1]; e2 = A[2];
 }
 
 template <int TILE, int BATCH>
@@ -241,13 +238,21 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
     return ballot64(!all) == 0ull;
   };
 
-  // next batch's entries, gathered from global memory into registers while
-  // the current batch is composited
+  // the next batch's records are gathered into registers while the current
+  // batch is composited, and the ids of the batch after it one batch ahead
+  // (list positions are clamped to the list; the extra loads go unused)
   float4 p0[PER], p1[PER], p2[PER];
+  bool pok[PER];
+  uint32_t pid[PER];
+  const int n_rec = vw.n_rec, rec_base = vw.rec_base;
+  if (end > start) {
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int i = threadIdx.x + k * NT;
-    if (i < BATCH && start + i < end) load_entry(ws, vw, ws.ids[start + i], p0[k], p1[k], p2[k]);
+    for (int k = 0; k < PER; k++) pid[k] = ws.ids[min(start + (int)threadIdx.x + k * NT, end - 1)];
+#pragma unroll
+    for (int k = 0; k < PER; k++) fetch_record(ws, n_rec, rec_base, pid[k], p0[k], p1[k], p2[k], pok[k]);
+#pragma unroll
+    for (int k = 0; k < PER; k++)
+      pid[k] = ws.ids[min(start + BATCH + (int)threadIdx.x + k * NT, end - 1)];
   }
 
   for (int b = start; b < end; b += BATCH) {
@@ -265,15 +270,16 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
         e0s[i] = make_float4(p0[k].x, p0[k].y, p0[k].z, 2.0f * p0[k].w);
         e1s[i] = p1[k]; e2s[i] = p2[k];
       }
-      stage_masks<TILE, NCH>(masks, i, have, p0[k], p1[k].x, p1[k].w, qcut, (float)ox, (float)oy);
+      stage_masks<TILE, NCH>(masks, i, have && pok[k], p0[k], p1[k].x, p1[k].w, qcut, (float)ox,
+                             (float)oy);
     }
     __syncthreads();
-    const int nx = b + BATCH;
+    // (past the last batch the clamped loads repeat the list's last entry)
 #pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int i = threadIdx.x + k * NT;
-      if (i < BATCH && nx + i < end) load_entry(ws, vw, ws.ids[nx + i], p0[k], p1[k], p2[k]);
-    }
+    for (int k = 0; k < PER; k++) fetch_record(ws, n_rec, rec_base, pid[k], p0[k], p1[k], p2[k], pok[k]);
+#pragma unroll
+    for (int k = 0; k < PER; k++)
+      pid[k] = ws.ids[min(b + 2 * BATCH + (int)threadIdx.x + k * NT, end - 1)];
     if (wave_done()) continue;
     const uint32_t base = (uint32_t)(b - start + 1);
     const int nch = (nb + kWave - 1) / kWave;
@@ -388,35 +394,32 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
 }
 
 // Backward staging of one list entry: the forward record, the camera-frame
-// centre and learnable flag, and (slot mode) the entry's (record, tile) slot.
+// centre and learnable flag, and (slot mode) the record's tile rectangle and
+// first slot.  Gathered without branches, as in the forward.
 struct BwdEntry {
   float4 e0, e1, e2, eb;
-  uint32_t slot;
+  uint2 rc;
+  uint32_t off;
+  bool ok;
 };
 
 template <bool kSlots>
-__device__ __forceinline__ void load_bwd_entry(const Ws &ws, const DevView &vw, uint32_t id, int tx,
-                                               int ty, BwdEntry &E) {
-  if (id < (uint32_t)vw.n_rec) {
-    const int rec = vw.rec_base + (int)id;
-    const float4 *A = ws.recA + 3 * (int64_t)rec;
-    E.e0 = A[0]; E.e1 = A[1]; E.e2 = A[2];
-    E.eb = ws.recB[rec];
-    E.slot = 0xffffffffu;
-    if (kSlots) {
-      const uint2 rc = ws.rect[rec];
-      const int x0 = rc.x & 0xffff, y0 = rc.x >> 16, x1 = rc.y & 0xffff;
-      const uint32_t sl = ws.rec_off[rec] + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
-      if (sl < (uint64_t)ws.cap) E.slot = sl;
-      else E.eb.z = 0.f;  // only after a capacity overflow
-    }
-  } else {
-    E.e0 = make_float4(-1e30f, -1e30f, 0.f, 0.f);
-    E.e1 = make_float4(0.f, 0.f, 1.f, 0.f);
-    E.e2 = make_float4(0.f, 0.f, 0.f, 0.f);
-    E.eb = make_float4(0.f, 0.f, 0.f, 0.f);
-    E.slot = 0xffffffffu;
-  }
+__device__ __forceinline__ void fetch_bwd_entry(const Ws &ws, int n_rec, int rec_base, uint32_t id,
+                                                BwdEntry &E) {
+  E.ok = id < (uint32_t)n_rec;
+  const int64_t rec = (int64_t)rec_base + (E.ok ? id : 0u);
+  const float4 *A = ws.recA + 3 * rec;
+  E.e0 = A[0]; E.e1 = A[1]; E.e2 = A[2];
+  E.eb = ws.recB[rec];
+  if (kSlots) { E.rc = ws.rect[rec]; E.off = ws.rec_off[rec]; }
+}
+
+// The (record, tile) slot of a staged entry of tile (tx, ty), or ~0u when
+// it has none (an id out of range, or past the capacity after an overflow).
+__device__ __forceinline__ uint32_t entry_slot(const Ws &ws, const BwdEntry &E, int tx, int ty) {
+  const int x0 = E.rc.x & 0xffff, y0 = E.rc.x >> 16, x1 = E.rc.y & 0xffff;
+  const uint32_t sl = E.off + (uint32_t)((ty - y0) * (x1 - x0 + 1) + (tx - x0));
+  return E.ok && sl < (uint64_t)ws.cap ? sl : 0xffffffffu;
 }
 
 template <int TILE, int BATCH, int MODE>
@@ -514,14 +517,24 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   // batches on the forward's grid (start + multiples of BATCH), so each
   // 64-entry chunk is the forward's chunk and its lane bits apply
   const int nbat = (stop - start + BATCH - 1) / BATCH;
+  // the batch below is gathered while the current one is replayed, and its
+  // ids one batch ahead (positions clamped to the list, extra loads unused)
   BwdEntry st[PER];
+  uint32_t pid[PER];
+  const int n_rec = vw.n_rec, rec_base = vw.rec_base;
+  // position of this thread's entry k in the batch starting at `blo`,
+  // clamped to the list (batches below the first repeat its first entry)
+  auto bpos = [&](int blo, int k) {
+    return max(blo + min((int)threadIdx.x + k * NT, BATCH - 1), start);
+  };
   if (nbat > 0) {
     const int lo = start + (nbat - 1) * BATCH;
 #pragma unroll
-    for (int k = 0; k < PER; k++) {
-      const int i = threadIdx.x + k * NT;
-      if (i < BATCH && lo + i < stop) load_bwd_entry<kSlots>(ws, vw, ws.ids[lo + i], tx, ty, st[k]);
-    }
+    for (int k = 0; k < PER; k++) pid[k] = ws.ids[min(lo + (int)threadIdx.x + k * NT, stop - 1)];
+#pragma unroll
+    for (int k = 0; k < PER; k++) fetch_bwd_entry<kSlots>(ws, n_rec, rec_base, pid[k], st[k]);
+#pragma unroll
+    for (int k = 0; k < PER; k++) pid[k] = ws.ids[bpos(lo - BATCH, k)];
   }
   for (int bi = nbat - 1; bi >= 0; bi--) {
     const int lo = start + bi * BATCH;
@@ -530,8 +543,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
 #pragma unroll
     for (int k = 0; k < PER; k++) {
       const int i = threadIdx.x + k * NT;
-      stage_masks<TILE, NCH>(masks, i, i < nb, st[k].e0, st[k].e1.x, st[k].e1.w, qcut, (float)ox,
-                             (float)oy);
+      stage_masks<TILE, NCH>(masks, i, i < nb && st[k].ok, st[k].e0, st[k].e1.x, st[k].e1.w, qcut,
+                             (float)ox, (float)oy);
       if (i >= nb) continue;
       const BwdEntry &E = st[k];
       // the doubled off-diagonal conic term (exact) for q, the plain one
@@ -541,9 +554,12 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       e2s[i] = E.e2;
       const float iz = 1.0f / E.e1.z;
       ejs[i] = make_float4(vfx * iz, vfy * iz, -vfx * E.eb.x * iz * iz, -vfy * E.eb.y * iz * iz);
-      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, E.eb.z);
+      const uint32_t sl = kSlots ? entry_slot(ws, E, tx, ty) : 0xffffffffu;
+      // no slot (only after a capacity overflow): the entry learns nothing
+      const float learn = !kSlots || sl != 0xffffffffu ? E.eb.z : 0.f;
+      eps_[i] = make_float4(E.eb.x, E.eb.y, 2.0f * E.e2.w * E.e2.w * iz, learn);
       if (kSlots) {
-        slot_s[i] = E.slot;
+        slot_s[i] = sl;
 #pragma unroll
         for (int ww = 0; ww < NW; ww++)
 #pragma unroll
@@ -551,14 +567,11 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       }
     }
     __syncthreads();
-    if (bi > 0) {  // the batch below is a full one
-      const int nlo = lo - BATCH;
+    // the batches below are full ones (below the first: clamped, unused)
 #pragma unroll
-      for (int k = 0; k < PER; k++) {
-        const int i = threadIdx.x + k * NT;
-        if (i < BATCH) load_bwd_entry<kSlots>(ws, vw, ws.ids[nlo + i], tx, ty, st[k]);
-      }
-    }
+    for (int k = 0; k < PER; k++) fetch_bwd_entry<kSlots>(ws, n_rec, rec_base, pid[k], st[k]);
+#pragma unroll
+    for (int k = 0; k < PER; k++) pid[k] = ws.ids[bpos(lo - 2 * BATCH, k)];
     // this wave's entries, last to first, below its own last contributor
     const int lim = min(nb, wstop - lo);
     const int ctop = (lim - 1) / kWave;
@@ -677,9 +690,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
     // list entries past every pixel's last contributor: zero slots
     for (int i = stop + (int)threadIdx.x; i < end; i += NT) {
       BwdEntry E;
-      load_bwd_entry<true>(ws, vw, ws.ids[i], tx, ty, E);
-      if (E.slot == 0xffffffffu) continue;
-      float *o = ws.slots + 5 * (int64_t)E.slot;
+      fetch_bwd_entry<true>(ws, n_rec, rec_base, ws.ids[i], E);
+      const uint32_t sl = entry_slot(ws, E, tx, ty);
+      if (sl == 0xffffffffu) continue;
+      float *o = ws.slots + 5 * (int64_t)sl;
 #pragma unroll
       for (int c = 0; c < 5; c++) o[c] = 0.f;
     }

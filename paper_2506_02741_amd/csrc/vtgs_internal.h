@@ -100,7 +100,7 @@ struct Ws {
   uint32_t *last;              // [P] contributors end (relative to tile start)
   float *img;                  // [5][P] internal rgb(3), depth, sil
   float *gimg;                 // [5][P] internal upstream gradients
-  float *twist_part;           // [n_tiles][6]
+  float *twist_part;           // [n_tiles][8]: six twist sums, the Eq. 1 loss, one unused
   float *loss_part;            // [n_views][loss_blocks][4]
   float *ssim_map;             // [3 kinds][3 ch][P]
   float *ssim_part;            // [n_views][3][loss_blocks]

@@ -581,41 +581,46 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, ui
       tie |= l * E + e + 1 < n && (uint32_t)(k[e] >> 32) == (uint32_t)(k[e + 1] >> 32);
     tie |= l + 1 < kWave && l * E + E < n && (uint32_t)(k[E - 1] >> 32) == nxt;
     if (ballot64(tie) != 0ull) {
-      // runs of equal depth: each put in id order by the lane holding its
-      // first key (insertion sort), unless one is longer than 64, in which
-      // case every varying nibble (id, then depth) is sorted by radix
-      bool long_run = false;
+      // runs of equal depth, put in id order by odd-even transposition
+      // between neighbours of equal depth (runs are short: a round per key
+      // of the longest run); past 64 rounds, every varying nibble (id, then
+      // depth) is sorted by radix instead.  Padding keys (~0) tie with no
+      // real key, a real depth being below the infinity bits.
+      bool more = true;
+      for (int round = 0; more && round < 64; round++) {
+        bool sw = false;
 #pragma unroll
-      for (int e = 0; e < E; e++) {
-        const int i = l * E + e;
-        if (i + 1 >= n) continue;
-        const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
-        if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
-            (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
-        int len = 2;
-        while (i + len < n && len <= 64 && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
-        long_run = long_run || len > 64;
+        for (int ph = 0; ph < 2; ph++) {
+#pragma unroll
+          for (int e = ph; e + 1 < E; e += 2) {
+            const bool x = (uint32_t)(k[e] >> 32) == (uint32_t)(k[e + 1] >> 32) && k[e] > k[e + 1];
+            const unsigned long long lo = x ? k[e + 1] : k[e], hi = x ? k[e] : k[e + 1];
+            k[e] = lo; k[e + 1] = hi;
+            sw |= x;
+          }
+          if (ph == 1) {  // across lanes: (last of lane l, first of lane l + 1)
+            const unsigned long long nx =
+                ((unsigned long long)(uint32_t)__shfl_down((int)(uint32_t)(k[0] >> 32), 1) << 32) |
+                (uint32_t)__shfl_down((int)(uint32_t)k[0], 1);
+            const unsigned long long pv =
+                ((unsigned long long)(uint32_t)__shfl_up((int)(uint32_t)(k[E - 1] >> 32), 1) << 32) |
+                (uint32_t)__shfl_up((int)(uint32_t)k[E - 1], 1);
+            const bool xd = l + 1 < kWave && (uint32_t)(k[E - 1] >> 32) == (uint32_t)(nx >> 32) &&
+                            k[E - 1] > nx;
+            const bool xu = l > 0 && (uint32_t)(pv >> 32) == (uint32_t)(k[0] >> 32) && pv > k[0];
+            k[E - 1] = xd ? nx : k[E - 1];
+            k[0] = xu ? pv : k[0];
+            sw |= xd | xu;
+          }
+        }
+        more = ballot64(sw) != 0ull;
       }
-      if (ballot64(long_run) != 0ull) {
+      if (more) {
         wave_radix_passes<E>(k, diff & 0x00000000FFFFFFFFull, buf, starts);
         wave_radix_passes<E>(k, diff & 0xFFFFFFFF00000000ull, buf, starts);
       } else {
 #pragma unroll
-        for (int e = 0; e < E; e++) {
-          const int i = l * E + e;
-          if (i + 1 >= n) continue;
-          const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
-          if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
-              (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
-          int len = 2;
-          while (i + len < n && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
-          for (int a = i + 1; a < i + len; a++) {
-            const unsigned long long v = buf[lds_pos(a)];
-            int b = a - 1;
-            while (b >= i && buf[lds_pos(b)] > v) { buf[lds_pos(b + 1)] = buf[lds_pos(b)]; b--; }
-            buf[lds_pos(b + 1)] = v;
-          }
-        }
+        for (int e = 0; e < E; e++) buf[lds_pos(l * E + e)] = k[e];
         __syncthreads();
       }
     }

@@ -100,6 +100,17 @@ __global__ __launch_bounds__(kUpdNT) void k_track_update(Ws ws, vtgs_track_cfg c
   __shared__ float part[kUpdNT / kWave][7];
   const int v = blockIdx.x;
   const DevView &vw0 = ws.views[v];
+  // the pose, its Adam state and the iteration count, read before the sums
+  // so that their latency overlaps the reduction (thread 0 uses them)
+  float T[12], S[13];
+  int iter = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 12; i++) T[i] = vw0.pose[i];
+#pragma unroll
+    for (int i = 0; i < 13; i++) S[i] = vw0.pose_adam[i];
+    iter = *ws.iter;
+  }
   float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int i = threadIdx.x; i < vw0.n_tiles; i += kUpdNT) {
     const float *tp = ws.twist_part + 8 * (int64_t)(vw0.tile_base + i);
@@ -120,26 +131,25 @@ __global__ __launch_bounds__(kUpdNT) void k_track_update(Ws ws, vtgs_track_cfg c
     L += part[w][6];
   }
   const DevView &vw = ws.views[v];
-  if (loss) loss[(int64_t)(*ws.iter) * ws.n_views + v] = L;
+  if (loss) loss[(int64_t)iter * ws.n_views + v] = L;
   bool finite = __builtin_isfinite(L);
   for (int c = 0; c < 6; c++) finite &= __builtin_isfinite(g[c]);
   if (!finite) { atomicOr(ws.flags, kFlagNonfinite); return; }
   float *st = vw.pose_adam;
-  const float t = st[12] + 1.f;
+  const float t = S[12] + 1.f;
   st[12] = t;
   const float c1 = 1.f - powf(kB1, t), c2 = 1.f - powf(kB2, t);
   float xi[6];
   for (int i = 0; i < 6; i++) {
-    const float m = kB1 * st[i] + (1.f - kB1) * g[i];
-    const float s = kB2 * st[6 + i] + (1.f - kB2) * g[i] * g[i];
+    const float m = kB1 * S[i] + (1.f - kB1) * g[i];
+    const float s = kB2 * S[6 + i] + (1.f - kB2) * g[i] * g[i];
     st[i] = m;
     st[6 + i] = s;
     const float lr = i < 3 ? cfg.lr_trans : cfg.lr_rot;
     xi[i] = -lr * (m / c1) / (sqrtf(s / c2) + kEps);
   }
-  float E[12], T[12], N[12];
+  float E[12], N[12];
   se3_exp(xi, E);
-  for (int i = 0; i < 12; i++) T[i] = vw.pose[i];
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 4; j++) {
       float s = E[4 * i + 0] * T[j] + E[4 * i + 1] * T[4 + j] + E[4 * i + 2] * T[8 + j];

@@ -299,24 +299,38 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
         for (int k = 0; k < PPT; k++) own_lo[k] = own_hi[k] = 0u;
         for (int h = 0; h < 2; h++) {
           uint32_t mh = (uint32_t)(m >> (32 * h));
-          while (mh) {  // two entries per step, both loads issued first
-            const int ja = __builtin_ctz(mh);
-            mh &= mh - 1u;
-            const bool hb = mh != 0u;
-            const int jb = hb ? __builtin_ctz(mh) : ja;
-            mh &= hb ? mh - 1u : mh;
-            const int ia = c * kWave + 32 * h + ja, ib = c * kWave + 32 * h + jb;
-            const float4 a0 = e0s[ia], b0 = e0s[ib];
-            const float aq = e1s[ia].x, bq = e1s[ib].x;
+          while (mh) {  // four entries per step, all loads issued first
+            // past the last set bit: entry 31 of the half, whose bit the
+            // chunk mask clears below unless it is a visited entry anyway
+            int j[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              j[u] = __builtin_ctz(mh | 0x80000000u);
+              mh &= mh - 1u;
+            }
+            float4 a[4];
+            float aq[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              const int ia = c * kWave + 32 * h + j[u];
+              a[u] = e0s[ia];
+              aq[u] = e1s[ia].x;
+            }
 #pragma unroll
             for (int k = 0; k < PPT; k++) {
-              const float qa = quad2(a0, aq, px[k], py[k]);
-              const float qb = quad2(b0, bq, px[k], py[k]);
-              const uint32_t bits = ((!done[k] && qa <= qcut) ? (1u << ja) : 0u) |
-                                    ((!done[k] && qb <= qcut) ? (1u << jb) : 0u);
+              uint32_t bits = 0u;
+#pragma unroll
+              for (int u = 0; u < 4; u++)
+                bits |= (uint32_t)(quad2(a[u], aq[u], px[k], py[k]) <= qcut) << j[u];
+              bits = done[k] ? 0u : bits;
               if (h == 0) own_lo[k] |= bits; else own_hi[k] |= bits;
             }
           }
+        }
+#pragma unroll
+        for (int k = 0; k < PPT; k++) {
+          own_lo[k] &= (uint32_t)m;
+          own_hi[k] &= (uint32_t)(m >> 32);
         }
         {
           // kept for the backward, which replays the same chunks

@@ -88,10 +88,11 @@ __device__ __forceinline__ void block_of(int ww, int &x0, int &y0) {
 // widened by 2 % so that the FP32 value of q can never pass the cut outside
 // it.  A conic that is not positive definite gets no circle (box test only).
 __device__ __forceinline__ float cull_r2(float qa, float qb, float qc, float qcut) {
+  // (hardware square root and reciprocal, ~1 ulp: far inside the 2 %)
   const float h = 0.5f * (qa - qc);
-  const float lmax = 0.5f * (qa + qc) + sqrtf(fmaf(h, h, qb * qb));
+  const float lmax = 0.5f * (qa + qc) + __builtin_amdgcn_sqrtf(fmaf(h, h, qb * qb));
   const float det = fmaf(qa, qc, -qb * qb);
-  return det > 0.f ? 1.0201f * qcut * lmax / det : 3.0e38f;
+  return det > 0.f ? 1.0201f * qcut * lmax * __builtin_amdgcn_rcpf(det) : 3.0e38f;
 }
 
 // Wave masks of a staged batch: bit (i % 64) of masks[ww][i / 64] is set
@@ -597,20 +598,31 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       uint32_t ns[PPT], seq[PPT];
 #pragma unroll
       for (int k = 0; k < PPT; k++) ns[k] = seq[k] = 0u;
-      for (int c = min(g0 + G - 1, ctop); c >= g0; c--) {
+      // the group's lane bits, all loads issued at once (chunks past the top
+      // one reload the top one's, unused)
+      unsigned long long lb[G][PPT];
+#pragma unroll
+      for (int cc = 0; cc < G; cc++) {
+        const unsigned long long *src =
+            ws.lane_bits + chunk_word(start, lo - start, min(g0 + cc, ctop), t, w, NW, PPT);
+#pragma unroll
+        for (int k = 0; k < PPT; k++) lb[cc][k] = src[k * kWave + lane_id()];
+      }
+#pragma unroll
+      for (int cc = G - 1; cc >= 0; cc--) {
+        const int c = g0 + cc;
+        if (c > ctop) continue;
         unsigned long long m = uniform_u64(masks[w][c]);
         const int top = lim - c * kWave;  // entries [c*64, c*64 + top) are below the limit
         if (top < kWave) m &= (1ull << top) - 1ull;
         if (m == 0ull) continue;
-        const unsigned long long *src =
-            ws.lane_bits + chunk_word(start, lo - start, c, t, w, NW, PPT);
         const int base = lo - start + c * kWave;
 #pragma unroll
         for (int k = 0; k < PPT; k++) {
           const int lim_k = (int)last[k] - base;
           const unsigned long long below =
               lim_k >= kWave ? ~0ull : (lim_k <= 0 ? 0ull : (1ull << lim_k) - 1ull);
-          const unsigned long long own = src[k * kWave + lane_id()] & below & m;
+          const unsigned long long own = lb[cc][k] & below & m;
           const uint32_t hh = 2u * (uint32_t)(c - g0);
           push_word<NS, NR>(words, w * PPT + k, __builtin_bitreverse32((uint32_t)(own >> 32)),
                             hh + 1u, ns[k], seq[k]);

@@ -412,9 +412,11 @@ def main():
     value = 640 * 480 * args.steps / dt / 1e6
 
     # per-stage durations from HIP events on the launch stream (eager
-    # launches while timing is on)
+    # launches while timing is on; each compositing stage is launched 10
+    # times back to back between its events, so that its per-launch time
+    # leaves out the events' own overhead)
     log("bench: stage timing")
-    plan.timing(True)
+    plan.timing(True, repeat=10)
     with torch.cuda.stream(stream):
         run_frames(plan, view, init, cfg, 80, loss)
     stages = plan.timing(False)

@@ -214,6 +214,9 @@ int vtgs_map_step(vtgs_plan *plan, const vtgs_map_cfg *cfg, int32_t *step, float
 /* ---- measurement ----------------------------------------------------------
  * Stage timing: enable != 0 starts recording HIP events on the call's stream
  * around every stage the plan launches (preprocess, sort, compositing, ...);
+ * with enable = R > 1 (at most 64) the two compositing stages, which only
+ * overwrite what they write, are launched R times back to back between their
+ * events, so that the per-launch time leaves out the events' own overhead.
  * enable == 0 stops, synchronises those events and writes, per stage index
  * s < VTGS_N_STAGES, the summed milliseconds ms[s] and launches count[s]
  * (either array may be NULL).  vtgs_stage_name(s) names stage s. */

@@ -107,7 +107,9 @@ struct vtgs_plan {
   float *graph_loss = nullptr;
   vtgs_track_cfg graph_cfg{};
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_used;  // stage, (start, stop)
+  struct EvUse { int stage; size_t start, stop; int launches; };
+  std::vector<EvUse> ev_used;  // recorded stage intervals
+  int timing_repeat = 1;       // launches per compositing stage while timing
 };
 
 namespace {
@@ -256,22 +258,27 @@ hipError_t event_at(vtgs_plan *p, size_t i, hipEvent_t *e) {
   return hipSuccess;
 }
 
-// Launch `expr` as stage `stg`, bracketed by events when timing is on.
+// Launch `expr` as stage `stg`, bracketed by events when timing is on.  A
+// compositing stage (idempotent: it overwrites what it writes) is launched
+// `timing_repeat` times between its events, so that its per-launch time
+// leaves out the events' own overhead.
 #define STAGE(p, stg, st, expr)                                                  \
   do {                                                                           \
     size_t i0_ = 0;                                                              \
+    int rep_ = 1;                                                                \
     if ((p)->timing) {                                                           \
       hipEvent_t ev_;                                                             \
       i0_ = (p)->ev_used.size() * 2;                                             \
       HIP_OK(event_at((p), i0_, &ev_));                                           \
       HIP_OK(hipEventRecord(ev_, (st)));                                          \
+      if ((stg) == ST_FWD || (stg) == ST_BWD) rep_ = (p)->timing_repeat;         \
     }                                                                            \
-    HIP_OK(expr);                                                                \
+    for (int r_ = 0; r_ < rep_; r_++) HIP_OK(expr);                             \
     if ((p)->timing) {                                                           \
       hipEvent_t ev_;                                                             \
       HIP_OK(event_at((p), i0_ + 1, &ev_));                                       \
       HIP_OK(hipEventRecord(ev_, (st)));                                          \
-      (p)->ev_used.push_back({(stg), {i0_, i0_ + 1}});                           \
+      (p)->ev_used.push_back({(stg), i0_, i0_ + 1, rep_});                       \
     }                                                                            \
   } while (0)
 
@@ -695,6 +702,7 @@ int vtgs_plan_timing(vtgs_plan *p, int32_t enable, double *ms, int64_t *count) {
     if (!p) return fail(VTGS_E_ARG, "plan_timing: plan is NULL");
     if (enable) {
       p->timing = true;
+      p->timing_repeat = enable > 1 ? std::min(enable, 64) : 1;
       p->ev_used.clear();
       return VTGS_OK;
     }
@@ -702,11 +710,11 @@ int vtgs_plan_timing(vtgs_plan *p, int32_t enable, double *ms, int64_t *count) {
     double acc[ST_N] = {0};
     int64_t cnt[ST_N] = {0};
     for (auto &u : p->ev_used) {
-      HIP_OK(hipEventSynchronize(p->ev_pool[u.second.second]));
+      HIP_OK(hipEventSynchronize(p->ev_pool[u.stop]));
       float t = 0.f;
-      HIP_OK(hipEventElapsedTime(&t, p->ev_pool[u.second.first], p->ev_pool[u.second.second]));
-      acc[u.first] += t;
-      cnt[u.first] += 1;
+      HIP_OK(hipEventElapsedTime(&t, p->ev_pool[u.start], p->ev_pool[u.stop]));
+      acc[u.stage] += t;
+      cnt[u.stage] += u.launches;
     }
     p->ev_used.clear();
     for (int i = 0; i < ST_N; i++) {

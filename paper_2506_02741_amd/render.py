@@ -275,12 +275,13 @@ class Plan:
         rc = self.L.vtgs_plan_status(self.h, C.byref(need), 1 if clear else 0, _stream(stream))
         return rc, int(need.value)
 
-    def timing(self, enable):
+    def timing(self, enable, repeat=1):
         """Start (enable=True) or stop per-stage HIP-event timing; stopping
-        returns {stage: (total_ms, launches)}."""
+        returns {stage: (total_ms, launches)}.  `repeat` > 1 launches each
+        compositing stage that many times between its events."""
         import numpy as np
         if enable:
-            check(self.L.vtgs_plan_timing(self.h, 1, None, None))
+            check(self.L.vtgs_plan_timing(self.h, max(1, int(repeat)), None, None))
             return None
         ms = np.zeros(_lib.VTGS_N_STAGES, np.float64)
         cnt = np.zeros(_lib.VTGS_N_STAGES, np.int64)

@@ -263,3 +263,35 @@ def test_batched_fwd_bwd_graph_replay_equals_eager(R):
             assert torch.equal(a, b), rep
         plan.render_fwd()          # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_stage_timing_with_repeats_changes_nothing(R):
+    """Stage timing that launches each compositing stage several times
+    counts every launch and leaves the images and gradients bit for bit as
+    without timing (the compositing stages overwrite what they write)."""
+    import numpy as np
+    import torch
+    from scenes import room_frames
+    cam, frames, _ = room_frames(11, 96, 72, n_kf=2)
+    ks = [R.Keyframe.ingest(f.depth, f.rgb, cam.as_tuple(), f.pose, learnable=True).with_grad_buffers()
+          for f in frames]
+    plan = R.Plan(ks, [R.View(cam.as_tuple(), f.pose, 0, 2) for f in frames])
+    rng = np.random.default_rng(3)
+    g = torch.tensor(rng.normal(size=(3, plan.P)), dtype=torch.float32, device="cuda")
+
+    def run():
+        for k in ks:
+            k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+        img = [x.clone() for x in plan.render_fwd()]
+        plan.render_bwd(g, None, None, twist=False)
+        torch.cuda.synchronize()
+        return img + [t.clone() for k in ks for t in (k.g_color, k.g_opacity, k.g_radius)]
+    ref = run()
+    plan.timing(True, repeat=3)
+    got = run()
+    stages = plan.timing(False)
+    assert plan.status()[0] == 0
+    assert stages["composite_fwd"][1] == 3 and stages["composite_bwd"][1] == 3, stages
+    assert stages["preprocess"][1] == 1, stages
+    for a, b in zip(got, ref):
+        assert torch.equal(a, b)

@@ -106,8 +106,18 @@ __device__ __forceinline__ unsigned long long box_ballot(const WaveBox &b, int j
   return ballot64(in);
 }
 
+constexpr int kSegLds = 1024;  // segment starts the preprocess keeps in LDS
+
 __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   const int r = blockIdx.x * kNT + threadIdx.x;
+  // the segments' first records, read by the block at once, then searched
+  // in LDS (plans with more segments search them in global memory)
+  __shared__ int seg_start[kSegLds];
+  const bool seg_lds = ws.n_segs <= kSegLds;
+  if (seg_lds) {
+    for (int k = threadIdx.x; k < ws.n_segs; k += kNT) seg_start[k] = ws.segs[k].rec_start;
+    __syncthreads();
+  }
   // one more pass of the pipeline: the tracking update writes its loss at
   // this index, so a captured iteration needs no per-iteration argument
   if (r == 0) *ws.iter += 1u;
@@ -115,33 +125,53 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   bool has = false;
   int view = 0, x0 = 1, y0 = 0, x1 = 0, y1 = 0, tiles_x = 1, tile_base = 0;
   if (active) {
-    const DevSeg &sg = ws.segs[find_seg(ws, r)];
+    int seg = 0;
+    if (seg_lds) {
+      int lo = 0, hi = ws.n_segs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] <= r) lo = mid; else hi = mid - 1;
+      }
+      seg = lo;
+    } else {
+      seg = find_seg(ws, r);
+    }
+    const DevSeg &sg = ws.segs[seg];
     const DevKF &kf = ws.kfs[sg.kf];
     const DevView &vw = ws.views[sg.view];
+    // the descriptor fields used below, read up front (not inside branches)
+    const float kfx = kf.fx, kfy = kf.fy, kcx = kf.cx, kcy = kf.cy;
+    const float vfx = vw.fx, vfy = vw.fy, vcx = vw.cx, vcy = vw.cy;
+    const int kwidth = kf.width, vtiles_y = vw.tiles_y;
     float M[12];
     relative_pose(vw.pose, kf.pose, M);
     view = sg.view;
     tiles_x = vw.tiles_x;
     tile_base = vw.tile_base;
     const int i = r - sg.rec_start;
+    // every per-Gaussian load issued together, before the arithmetic
     const uint32_t pix = kf.pix[i];
     const float d = kf.depth[i];
     const float rad = kf.radius[i];
-    const int u = (int)(pix % (uint32_t)kf.width), v = (int)(pix / (uint32_t)kf.width);
+    const float o = kf.opacity[i];
+    const float c0 = kf.color[i], c1 = kf.color[(int64_t)kf.n + i],
+                c2 = kf.color[2 * (int64_t)kf.n + i];
+    const float learn = kf.learnable ? 1.f : 0.f;
+    const int u = (int)(pix % (uint32_t)kwidth), v = (int)(pix / (uint32_t)kwidth);
     // back-projection of the tied depth pixel (keyframe camera)
-    const float xk = (((float)u - kf.cx) / kf.fx) * d;
-    const float yk = (((float)v - kf.cy) / kf.fy) * d;
+    const float xk = (((float)u - kcx) / kfx) * d;
+    const float yk = (((float)v - kcy) / kfy) * d;
     const float zk = d;
     const float px = ((M[0] * xk + M[1] * yk) + M[2] * zk) + M[3];
     const float py = ((M[4] * xk + M[5] * yk) + M[6] * zk) + M[7];
     const float pz = ((M[8] * xk + M[9] * yk) + M[10] * zk) + M[11];
     float mx = 0.f, my = 0.f, qa = 0.f, qb = 0.f, qc = 0.f, R = 0.f;
     if (pz > ws.znear) {
-      mx = vw.fx * (px / pz) + vw.cx;
-      my = vw.fy * (py / pz) + vw.cy;
-      const float a = vw.fx / pz, b = vw.fy / pz;
+      mx = vfx * (px / pz) + vcx;
+      my = vfy * (py / pz) + vcy;
+      const float a = vfx / pz, b = vfy / pz;
       const float zz = pz * pz;
-      const float jx = -(vw.fx * px) / zz, jy = -(vw.fy * py) / zz;
+      const float jx = -(vfx * px) / zz, jy = -(vfy * py) / zz;
       const float r2 = rad * rad;
       const float s11 = r2 * (a * a + jx * jx) + ws.lowpass;
       const float s12 = r2 * (jx * jy);
@@ -156,8 +186,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
           const float invB = 1.0f / (float)ws.tile;
           const float fx0 = fmaxf(floorf((mx - R) * invB), 0.f);
           const float fy0 = fmaxf(floorf((my - R) * invB), 0.f);
-          const float fx1 = fminf(floorf((mx + R) * invB), (float)(vw.tiles_x - 1));
-          const float fy1 = fminf(floorf((my + R) * invB), (float)(vw.tiles_y - 1));
+          const float fx1 = fminf(floorf((mx + R) * invB), (float)(tiles_x - 1));
+          const float fy1 = fminf(floorf((my + R) * invB), (float)(vtiles_y - 1));
           if (!(fx0 > fx1 || fy0 > fy1)) {
             x0 = (int)fx0; y0 = (int)fy0; x1 = (int)fx1; y1 = (int)fy1;
             has = true;
@@ -165,13 +195,11 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
         }
       }
     }
-    const float o = kf.opacity[i];
     float4 *A = ws.recA + 3 * (int64_t)r;
     A[0] = make_float4(mx, my, qa, qb);
     A[1] = make_float4(qc, o, pz, R);
-    A[2] = make_float4(kf.color[i], kf.color[(int64_t)kf.n + i], kf.color[2 * (int64_t)kf.n + i],
-                       rad);
-    ws.recB[r] = make_float4(px, py, kf.learnable ? 1.f : 0.f, 0.f);
+    A[2] = make_float4(c0, c1, c2, rad);
+    ws.recB[r] = make_float4(px, py, learn, 0.f);
     if (!has) { x0 = 1; y0 = 0; x1 = 0; y1 = 0; }
     ws.rect[r] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
     ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;

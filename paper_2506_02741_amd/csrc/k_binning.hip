@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   }
 }
 
-constexpr int kSmallSort = 2048;  // longer tile lists go to the long-list sort
+constexpr int kSmallSort = 768;  // longer tile lists go to the long-list sort
 
 // One block: tile counts -> ranges (clamped to the pair capacity), total
 // pairs, capacity flag; lists longer than kSmallSort are queued for the
@@ -347,151 +347,6 @@ __device__ __forceinline__ uint32_t field8(unsigned long long lo, unsigned long 
   return (uint32_t)(v >> (8 * (d & 7))) & 0xffu;
 }
 
-// Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
-// of the NT * E keys of a block.  Thread t holds keys t*E .. t*E+E-1 in
-// registers ("blocked" order).  Per pass each thread counts its keys per
-// digit in 8-bit fields, a DPP wave scan of the counts (as 16-bit fields)
-// and a pass over the wave totals in LDS give each thread its start in
-// every digit bucket, and the keys are scattered through `buf` in
-// thread-then-register order, which keeps each pass stable.  On return
-// buf[0 .. NT*E) and the registers hold the keys in the new order.
-template <int NT, int E>
-__device__ void radix_passes(unsigned long long (&k)[E], unsigned long long digits,
-                             unsigned long long *buf, uint32_t (*wsum)[8]) {
-  constexpr int NW = NT / kWave;
-  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
-  for (int sh = 0; sh < 64; sh += 4) {
-    if (((digits >> sh) & 15ull) == 0ull) continue;
-    int dg[E];
-    unsigned long long clo = 0ull, chi = 0ull;
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-      const int d = (int)((k[e] >> sh) & 15ull);
-      dg[e] = d;
-      const unsigned long long one = 1ull << (8 * (d & 7));
-      clo += d < 8 ? one : 0ull;
-      chi += d < 8 ? 0ull : one;
-    }
-    // counts as 16-bit fields: c[q] holds digits 2q and 2q + 1
-    uint32_t c[8], inc[8];
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      c[q] = field8(clo, chi, 2 * q) | (field8(clo, chi, 2 * q + 1) << 16);
-      inc[q] = wave_incl_scan_u32(c[q]);
-    }
-    if (l == kWave - 1) {
-#pragma unroll
-      for (int q = 0; q < 8; q++) wsum[w][q] = inc[q];
-    }
-    __syncthreads();
-    uint32_t start[8], tot[8];
-#pragma unroll
-    for (int q = 0; q < 8; q++) { start[q] = inc[q] - c[q]; tot[q] = 0u; }
-#pragma unroll
-    for (int i = 0; i < NW; i++) {
-#pragma unroll
-      for (int q = 0; q < 8; q++) {
-        const uint32_t v = wsum[i][q];
-        start[q] += i < w ? v : 0u;
-        tot[q] += v;
-      }
-    }
-    uint32_t run = 0u;
-#pragma unroll
-    for (int q = 0; q < 8; q++) {
-      const uint32_t a = tot[q] & 0xffffu, b = tot[q] >> 16;
-      start[q] += run | ((run + a) << 16);
-      run += a + b;
-    }
-    unsigned long long slo = 0ull, shi = 0ull;
-#pragma unroll
-    for (int e = 0; e < E; e++) {
-      const int d = dg[e];
-      uint32_t v = start[0];
-#pragma unroll
-      for (int q = 1; q < 8; q++) v = (d >> 1) == q ? start[q] : v;
-      const uint32_t pos = ((v >> (16 * (d & 1))) & 0xffffu) + field8(slo, shi, d);
-      const unsigned long long one = 1ull << (8 * (d & 7));
-      slo += d < 8 ? one : 0ull;
-      shi += d < 8 ? 0ull : one;
-      buf[min(pos, (uint32_t)(NT * E - 1))] = k[e];  // a permutation of 0 .. NT*E-1
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; e++) k[e] = buf[t * E + e];
-    __syncthreads();
-  }
-#pragma unroll
-  for (int e = 0; e < E; e++) buf[t * E + e] = k[e];
-  __syncthreads();
-}
-
-// Sort of the NT * E keys (depth bits << 32 | id) of a block; the first n
-// are the tile's, the rest ~0ull (maximal, and last, so they stay last).
-// Depth first: radix passes over the depth nibbles that vary.  Keys of equal
-// depth then form runs ordered by fill position; each run is put in id
-// order by one thread (insertion sort), unless some run is longer than 64,
-// in which case every varying nibble (id included) is sorted by radix
-// instead.  Either way buf[0 .. n) ends in ascending (depth, id) order.
-template <int NT, int E>
-__device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long long *buf,
-                               uint32_t (*wsum)[8], unsigned long long *red) {
-  constexpr int NW = NT / kWave;
-  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
-  unsigned long long orv = 0ull, andv = ~0ull;
-#pragma unroll
-  for (int e = 0; e < E; e++)
-    if (t * E + e < n) { orv |= k[e]; andv &= k[e]; }
-  for (int o = 32; o > 0; o >>= 1) {
-    orv |= __shfl_xor(orv, o);
-    andv &= __shfl_xor(andv, o);
-  }
-  if (l == 0) { red[2 * w] = orv; red[2 * w + 1] = andv; }
-  __syncthreads();
-  orv = 0ull; andv = ~0ull;
-#pragma unroll
-  for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
-  const unsigned long long diff = orv ^ andv;
-  radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum);
-  // runs of equal depth among the first n keys, found from their first key
-  bool long_run = false;
-#pragma unroll
-  for (int e = 0; e < E; e++) {
-    const int i = t * E + e;
-    if (i + 1 >= n) continue;
-    const uint32_t z = (uint32_t)(buf[i] >> 32);
-    if ((uint32_t)(buf[i + 1] >> 32) != z || (i > 0 && (uint32_t)(buf[i - 1] >> 32) == z)) continue;
-    int len = 2;
-    while (i + len < n && len <= 64 && (uint32_t)(buf[i + len] >> 32) == z) len++;
-    long_run = long_run || len > 64;
-  }
-  if (__syncthreads_or(long_run)) {
-    radix_passes<NT, E>(k, diff & 0x00000000FFFFFFFFull, buf, wsum);
-    radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum);
-    return;
-  }
-  // insertion sort of every run by id (the runs are disjoint)
-#pragma unroll
-  for (int e = 0; e < E; e++) {
-    const int i = t * E + e;
-    if (i + 1 >= n) continue;
-    const uint32_t z = (uint32_t)(buf[i] >> 32);
-    if ((uint32_t)(buf[i + 1] >> 32) != z || (i > 0 && (uint32_t)(buf[i - 1] >> 32) == z)) continue;
-    int len = 2;
-    while (i + len < n && (uint32_t)(buf[i + len] >> 32) == z) len++;
-    for (int a = i + 1; a < i + len; a++) {
-      const unsigned long long v = buf[a];
-      int b = a - 1;
-      while (b >= i && buf[b] > v) { buf[b + 1] = buf[b]; b--; }
-      buf[b + 1] = v;
-    }
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// One-wave tile sort (lists of up to 15 keys per lane)
-// ---------------------------------------------------------------------------
 // LDS slot of list position i: one spare slot after every 16, so that the
 // lanes reading positions t*E .. t*E+E-1 spread over the banks.
 __device__ __forceinline__ int lds_pos(int i) { return i + (i >> 4); }
@@ -514,6 +369,175 @@ __device__ __forceinline__ uint32_t wave_and_u32(uint32_t x) {
          ((uint32_t)__builtin_amdgcn_readlane((int)x, 32) & (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
 }
 
+// Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
+// of the NT * E keys of a block.  Thread t holds keys t*E .. t*E+E-1 in
+// registers ("blocked" order).  Per pass each thread counts its keys per
+// digit (4-bit fields of one u64 for E <= 15, else 8-bit fields of two), a
+// DPP wave scan of the counts (as 16-bit fields) and the wave totals in LDS
+// give each thread its start in every digit bucket (with E <= 15 parked in
+// `starts` so that each key fetches its own), and the keys are scattered
+// through `buf` (at lds_pos) in thread-then-register order, which keeps each
+// pass stable.  On return buf and the registers hold the keys in the new
+// order.
+template <int NT, int E>
+__device__ void radix_passes(unsigned long long (&k)[E], unsigned long long digits,
+                             unsigned long long *buf, uint32_t (*wsum)[8], uint32_t *starts) {
+  constexpr int NW = NT / kWave;
+  constexpr bool k4 = E <= 15;
+  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
+  for (int sh = 0; sh < 64; sh += 4) {
+    if (((digits >> sh) & 15ull) == 0ull) continue;
+    int dg[E];
+    unsigned long long clo = 0ull, chi = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = (int)((k[e] >> sh) & 15ull);
+      dg[e] = d;
+      if (k4) {
+        clo += 1ull << (4 * d);
+      } else {
+        const unsigned long long one = 1ull << (8 * (d & 7));
+        clo += d < 8 ? one : 0ull;
+        chi += d < 8 ? 0ull : one;
+      }
+    }
+    // counts as 16-bit fields: c[q] holds digits 2q and 2q + 1
+    uint32_t c[8], inc[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      if (k4) {
+        const uint32_t v = q < 4 ? (uint32_t)clo : (uint32_t)(clo >> 32);
+        const int o = 8 * (q & 3);
+        c[q] = ((v >> o) & 15u) | (((v >> (o + 4)) & 15u) << 16);
+      } else {
+        c[q] = field8(clo, chi, 2 * q) | (field8(clo, chi, 2 * q + 1) << 16);
+      }
+      inc[q] = wave_incl_scan_u32(c[q]);
+    }
+    if (l == kWave - 1) {
+#pragma unroll
+      for (int q = 0; q < 8; q++) wsum[w][q] = inc[q];
+    }
+    __syncthreads();
+    uint32_t start[8];
+    uint32_t run = 0u;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      uint32_t pre = 0u, tot = 0u;
+#pragma unroll
+      for (int i = 0; i < NW; i++) {
+        const uint32_t v = wsum[i][q];
+        pre += i < w ? v : 0u;
+        tot += v;
+      }
+      const uint32_t a = tot & 0xffffu;
+      start[q] = inc[q] - c[q] + pre + (run | ((run + a) << 16));
+      run += a + (tot >> 16);
+      if (k4) starts[q * NT + t] = start[q];
+    }
+    unsigned long long slo = 0ull, shi = 0ull;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const int d = dg[e];
+      uint32_t v, seen;
+      if (k4) {
+        v = starts[(d >> 1) * NT + t];
+        seen = (uint32_t)((slo >> (4 * d)) & 15ull);
+        slo += 1ull << (4 * d);
+      } else {
+        v = start[0];
+#pragma unroll
+        for (int q = 1; q < 8; q++) v = (d >> 1) == q ? start[q] : v;
+        seen = field8(slo, shi, d);
+        const unsigned long long one = 1ull << (8 * (d & 7));
+        slo += d < 8 ? one : 0ull;
+        shi += d < 8 ? 0ull : one;
+      }
+      const uint32_t pos = ((v >> (16 * (d & 1))) & 0xffffu) + seen;
+      buf[lds_pos((int)min(pos, (uint32_t)(NT * E - 1)))] = k[e];  // a permutation
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; e++) k[e] = buf[lds_pos(t * E + e)];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; e++) buf[lds_pos(t * E + e)] = k[e];
+  __syncthreads();
+}
+
+// Sort of the NT * E keys (depth bits << 32 | id) of a block; the first n
+// are the tile's, the rest ~0ull (maximal, and last, so they stay last; no
+// real key is ~0ull, its depth bits being below the infinity bits).  Depth
+// first: radix passes over the depth nibbles that vary.  Keys of equal depth
+// then form runs ordered by their earlier positions; each run is put in id
+// order by one thread (insertion sort), unless some run is longer than 64,
+// in which case every varying nibble (id included) is sorted by radix
+// instead.  Either way buf (at lds_pos) ends in ascending (depth, id) order.
+template <int NT, int E>
+__device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long long *buf,
+                               uint32_t (*wsum)[8], unsigned long long *red, uint32_t *starts) {
+  constexpr int NW = NT / kWave;
+  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
+  uint32_t olo = 0u, ohi = 0u, alo = ~0u, ahi = ~0u;
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const bool in = k[e] != ~0ull;
+    olo |= in ? (uint32_t)k[e] : 0u;
+    ohi |= in ? (uint32_t)(k[e] >> 32) : 0u;
+    alo &= in ? (uint32_t)k[e] : ~0u;
+    ahi &= in ? (uint32_t)(k[e] >> 32) : ~0u;
+  }
+  const unsigned long long orw = ((unsigned long long)wave_or_u32(ohi) << 32) | wave_or_u32(olo);
+  const unsigned long long andw = ((unsigned long long)wave_and_u32(ahi) << 32) | wave_and_u32(alo);
+  if (l == 0) { red[2 * w] = orw; red[2 * w + 1] = andw; }
+  __syncthreads();
+  unsigned long long orv = 0ull, andv = ~0ull;
+#pragma unroll
+  for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
+  const unsigned long long diff = orv ^ andv;
+  radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum, starts);
+  // runs of equal depth among the first n keys, found from their first key
+  bool long_run = false;
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int i = t * E + e;
+    if (i + 1 >= n) continue;
+    const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
+    if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
+        (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
+    int len = 2;
+    while (i + len < n && len <= 64 && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
+    long_run = long_run || len > 64;
+  }
+  if (__syncthreads_or(long_run)) {
+    radix_passes<NT, E>(k, diff & 0x00000000FFFFFFFFull, buf, wsum, starts);
+    radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum, starts);
+    return;
+  }
+  // insertion sort of every run by id (the runs are disjoint)
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int i = t * E + e;
+    if (i + 1 >= n) continue;
+    const uint32_t z = (uint32_t)(buf[lds_pos(i)] >> 32);
+    if ((uint32_t)(buf[lds_pos(i + 1)] >> 32) != z ||
+        (i > 0 && (uint32_t)(buf[lds_pos(i - 1)] >> 32) == z)) continue;
+    int len = 2;
+    while (i + len < n && (uint32_t)(buf[lds_pos(i + len)] >> 32) == z) len++;
+    for (int a = i + 1; a < i + len; a++) {
+      const unsigned long long v = buf[lds_pos(a)];
+      int b = a - 1;
+      while (b >= i && buf[lds_pos(b)] > v) { buf[lds_pos(b + 1)] = buf[lds_pos(b)]; b--; }
+      buf[lds_pos(b + 1)] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// One-wave tile sort (lists of up to 15 keys per lane)
+// ---------------------------------------------------------------------------
 // Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
 // of the 64 * E keys of a one-wave block, lane t holding keys t*E ..
 // t*E+E-1.  Per pass each lane counts its keys per digit in the 4-bit fields
@@ -693,29 +717,42 @@ __device__ __forceinline__ void bitonic_sort(T *s, int n) {
 template <int NT, int EE>
 __device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, uint32_t *dst, int n,
                                                unsigned long long *buf, uint32_t (*wsum)[8],
-                                               unsigned long long *red) {
+                                               unsigned long long *red, uint32_t *starts) {
   unsigned long long k[EE];
-  // every load first (clamped index), then the padding: no wait per load
+  // coalesced loads (any starting arrangement sorts to the same result, the
+  // keys being unique), every load first (clamped index), then the padding
 #pragma unroll
-  for (int e = 0; e < EE; e++) k[e] = src[min((int)threadIdx.x * EE + e, n - 1)];
+  for (int e = 0; e < EE; e++) k[e] = src[min((int)threadIdx.x + NT * e, n - 1)];
 #pragma unroll
-  for (int e = 0; e < EE; e++) k[e] = (int)threadIdx.x * EE + e < n ? k[e] : ~0ull;
-  block_sort_u64<NT, EE>(k, n, buf, wsum, red);
-  for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[i];
+  for (int e = 0; e < EE; e++) k[e] = (int)threadIdx.x + NT * e < n ? k[e] : ~0ull;
+  block_sort_u64<NT, EE>(k, n, buf, wsum, red, starts);
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[lds_pos(i)];
 }
+
+// Register tiers of the tile sort: keys per thread for a one-wave block
+// (4 and 12 one-wave sorts, 32 the block sort) and for the 512-thread
+// long-list block (6, 10 and 16); up to 15 keys per thread count digits in
+// 4-bit fields and fetch their bucket starts from LDS.
+template <int NT, int E>
+struct SortTiers {
+  static constexpr int E1 = NT == kWave ? E / 3 : E / 4 + E / 8;
+  static constexpr int E2 = NT == kWave ? E : E / 2 + E / 8;
+};
 
 // One block per tile: keys (depth bits << 32 | id) are unique within a tile,
 // so ascending key order is the (depth, id) order.  Each variant handles the
 // tiles whose length lies in (lo_n, hi_n]; a list is held in registers with
-// the fewest keys per thread that fit it (E / 8, E / 4 + E / 8 or E), and
-// longer than NT * E -> global memory.
+// the fewest keys per thread of the tiers that fit it, and longer than
+// NT * E -> global memory.
 template <int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, int queued) {
   constexpr int CAP = NT * E;
-  constexpr int E1 = E / 8, E2 = E / 4 + E / 8;
-  constexpr bool kWaveSort = NT == kWave && E2 <= 15;
-  __shared__ unsigned long long buf[CAP + (kWaveSort ? CAP / 16 : 0)];
-  __shared__ uint32_t starts[kWaveSort ? 8 * kWave : 1];
+  constexpr int E1 = SortTiers<NT, E>::E1, E2 = SortTiers<NT, E>::E2;
+  constexpr bool kWaveSort = NT == kWave && E <= 15;
+  // the keys (padded) and, for up to 15 keys per thread, the threads' bucket
+  // starts: separate arrays, so that the compiler sees they never alias
+  __shared__ unsigned long long buf[CAP + CAP / 16];
+  __shared__ uint32_t starts[8 * NT];
   __shared__ uint32_t wsum[NT / kWave][8];
   __shared__ unsigned long long red[2 * (NT / kWave)];
   // short lists: tile = block; long lists: blocks take queued tiles in turn
@@ -747,17 +784,18 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, in
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
     continue;
   }
-  if (kWaveSort && n <= NT * E1) {
-    wave_sort_tile<E1>(src, dst, n, buf, starts);
-  } else if (kWaveSort && n <= NT * E2) {
-    wave_sort_tile<E2>(src, dst, n, buf, starts);
-  } else if (n <= NT * E1) {
-    sort_tile_regs<NT, E1>(src, dst, n, buf, wsum, red);
-  } else if (n <= NT * E2) {
-    sort_tile_regs<NT, E2>(src, dst, n, buf, wsum, red);
-  } else if (n <= CAP) {
-    sort_tile_regs<NT, E>(src, dst, n, buf, wsum, red);
+  bool done = true;
+  if constexpr (kWaveSort) {
+    if (n <= NT * E1) wave_sort_tile<E1>(src, dst, n, buf, starts);
+    else if (n <= CAP) wave_sort_tile<E>(src, dst, n, buf, starts);
+    else done = false;
   } else {
+    if (n <= NT * E1) sort_tile_regs<NT, E1>(src, dst, n, buf, wsum, red, starts);
+    else if (n <= NT * E2) sort_tile_regs<NT, E2>(src, dst, n, buf, wsum, red, starts);
+    else if (n <= CAP) sort_tile_regs<NT, E>(src, dst, n, buf, wsum, red, starts);
+    else done = false;
+  }
+  if (!done) {
     unsigned long long *g = ws.keys_tmp + rg.x;
     for (int i = threadIdx.x; i < n; i += NT) g[i] = src[i];
     __syncthreads();
@@ -863,16 +901,16 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 }
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
-  // one wave per tile: 8, 12 or 32 keys per lane
+  // one wave per tile: 4 or 12 keys per lane
   hipLaunchKernelGGL((k_sort_tiles<kWave, kSmallSort / kWave>), dim3(ws.n_tiles), dim3(kWave), 0,
                      st, ws, 0, kSmallSort, 0);
-  // long lists, queued by the scan, taken in turn by 512-thread blocks: two
-  // per CU when the records' expected pairs per tile (a Gaussian of extent
-  // ~4-5 px covers about (1 + 10 / B)^2 tiles of side B) make long lists the
-  // rule, else a few blocks for the odd one (an empty queue ends them at once,
-  // and a smaller grid ends sooner)
+  // lists longer than 768, queued by the scan, taken in turn by 512-thread
+  // blocks (6, 10 or 16 keys per thread): two per CU's worth of the grid
+  // when the records' expected pairs per tile (a Gaussian of extent ~4-5 px
+  // covers about (1 + 10 / B)^2 tiles of side B) make long lists the rule,
+  // else a few blocks for the odd one (an empty queue ends them at once)
   const double per = (1.0 + 10.0 / ws.tile) * (1.0 + 10.0 / ws.tile);
-  const bool many = per * (double)ws.n_rec > 0.5 * kSmallSort * (double)ws.n_tiles;
+  const bool many = per * (double)ws.n_rec > 1024.0 * (double)ws.n_tiles;
   const int nlong = std::min(ws.n_tiles, many ? 512 : 16);
   hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(nlong), dim3(512), 0, st, ws,
                      kSmallSort, 0x7fffffff, 1);

@@ -730,9 +730,9 @@ __device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, ui
 }
 
 // Register tiers of the tile sort: keys per thread for a one-wave block
-// (4 and 12 one-wave sorts, 32 the block sort) and for the 512-thread
-// long-list block (6, 10 and 16); up to 15 keys per thread count digits in
-// 4-bit fields and fetch their bucket starts from LDS.
+// (4 and 12) and for the 512-thread long-list block (6, 10 and 16); up to
+// 15 keys per thread count digits in 4-bit fields and fetch their bucket
+// starts from LDS.
 template <int NT, int E>
 struct SortTiers {
   static constexpr int E1 = NT == kWave ? E / 3 : E / 4 + E / 8;

@@ -128,17 +128,6 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) 
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// q = d^T Q d in a fixed order (d = pixel - mu).
-__device__ __forceinline__ float quad(const float4 &e0, float qc, float px, float py, float &dx,
-                                      float &dy) {
-  dx = px - e0.x;
-  dy = py - e0.y;
-  float q = (e0.z * dx) * dx;
-  q = fmaf((2.0f * e0.w) * dx, dy, q);
-  q = fmaf(qc * dy, dy, q);
-  return q;
-}
-
 // First u64 of the lane bits of chunk c of the batch at list offset `boff`
 // (a multiple of 64) of tile t, wave w of nw, ppt pixels per lane.  Chunks
 // of consecutive tiles never share an index (the tile number is added to
@@ -149,8 +138,8 @@ __device__ __forceinline__ int64_t chunk_word(int start, int boff, int c, int t,
   return ((cid * nw + w) * ppt) * kWave;
 }
 
-// The same q from a staged entry whose off-diagonal term is already
-// doubled (e0.w = 2 qb): identical operations, identical bits.
+// q = d^T Q d (d = pixel - mu) in a fixed order, from a staged entry whose
+// off-diagonal term is already doubled (e0.w = 2 qb, exact in FP32).
 __device__ __forceinline__ float quad2(const float4 &e0, float qc, float px, float py) {
   const float dx = px - e0.x, dy = py - e0.y;
   float q = (e0.z * dx) * dx;

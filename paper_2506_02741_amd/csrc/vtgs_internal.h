@@ -147,28 +147,6 @@ __device__ __forceinline__ float row_sum(float x) {
   return x;
 }
 
-// Wave sums of five values at once (all 64 lanes active), by transposing
-// while reducing: permlane32_swap pairs (v0, v1), (v2, v3), (v4, 0) so that
-// one half-wave holds one value; permlane16_swap then leaves one value per
-// 16-lane row; a row sum finishes.  On return the totals sit in lanes 0, 16,
-// 32, 48 of t as (v0, v2, v1, v3) and in lane 0 of t4 as v4.  Fixed order.
-__device__ __forceinline__ void wave_sum5(float v0, float v1, float v2, float v3, float v4,
-                                          float &t, float &t4) {
-  const auto p01 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v0), __float_as_uint(v1),
-                                                    false, false);
-  const auto p23 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v2), __float_as_uint(v3),
-                                                    false, false);
-  const auto p4 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v4), 0u, false, false);
-  const float s01 = __uint_as_float(p01[0]) + __uint_as_float(p01[1]);
-  const float s23 = __uint_as_float(p23[0]) + __uint_as_float(p23[1]);
-  const float s4 = __uint_as_float(p4[0]) + __uint_as_float(p4[1]);
-  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(s01), __float_as_uint(s23),
-                                                  false, false);
-  const auto q4 = __builtin_amdgcn_permlane16_swap(__float_as_uint(s4), 0u, false, false);
-  t = row_sum(__uint_as_float(q[0]) + __uint_as_float(q[1]));
-  t4 = row_sum(__uint_as_float(q4[0]) + __uint_as_float(q4[1]));
-}
-
 // Wave minimum / maximum of an int (all 64 lanes active), returned as a
 // uniform value: row_ror 8, 4, 2, 1 within rows, then the four row results.
 __device__ __forceinline__ int wave_min_i(int x) {

@@ -9,8 +9,9 @@ splat forward -> Eq. 1 loss -> backward to the SE(3) twist -> Adam step and
 retraction.  A step is one such iteration; value = 640*480*steps / seconds.
 
 Also reported on the same JSON line:
-  roofline      the dominant kernel's achieved rate vs the MI355X peak,
-                from HIP events on the stream the kernels run on
+  roofline      the dominant kernel's algorithmic FP32 lane-ops per second
+                vs the VALU issue peak, its time from HIP events on the
+                stream the kernels run on
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
                 same workload
   batched       mapping-section batch (5 of 8 keyframes per iteration,
@@ -26,7 +27,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -60,17 +60,17 @@ def run_frames(plan, view, init, cfg, iters, loss):
         done += n
 
 
-def flops_per_pair():
-    """FP32 operations per contributing (pixel, Gaussian) pair, counted from
-    the compositing arithmetic (add, mul, min = 1; fma = 2; exp2, rcp = 1;
-    compares and selects not counted).  Forward: d (2), q (8), G (2), alpha
-    (2), transmittance (2), weight (1), colour and depth accumulation (8) =
-    25.  Backward to the twist: d and q (10), G (2), alpha (2), o G and
-    1 - alpha (2), T recovery (2), weight (1), dL/dalpha (15), the behind
-    accumulators (15), dL/dq (2), w = Q d and t = J^T w (11), dL/dp (16),
-    rho and phi sums (15) = 99.  Pairs that cover a pixel without
-    contributing are not counted (a lower bound on the work)."""
-    return dict(fwd_contrib=25, bwd_contrib=99)
+# Lane-ops per unit of the compositing kernels' algorithmic work: one FP32
+# VALU operation per lane, an exp counted as 4 (quarter rate).  Forward: an
+# entry a pixel steps past costs d (2), q (5) and the cut test (1) = 8; a
+# contributor adds exp, alpha, transmittance, the stop test and the colour
+# and depth accumulation, 22 in all.  Backward: 10 per entry stepped past;
+# 90 per contributor (alpha and T recovery, dL/dalpha against the behind
+# accumulators, dL/dq, dL/dmu and the twist chain).
+LANE_OPS = dict(fwd_skip=8, fwd_contrib=22, bwd_skip=10, bwd_contrib=90)
+# FP32 VALU issue rate without packed operations: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (one lane-op per lane per clock)
+PEAK_LANE_OPS_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "%s_tracking_640x480_traffic.txt")
@@ -104,16 +104,63 @@ def measured_traffic(stage="composite_bwd"):
         return None
 
 
-def pair_counts(w):
-    """Per-frame counts of tested / covering / contributing pairs from the
-    oracle's per-pixel lists (the workload's own numbers)."""
+def scan_counts(plan, width, height):
+    """Units the compositing launches of a one-view plan process, counted on
+    the host from the plan's own sorted tile lists and records (the state
+    the kernels read after a render): per pixel, the forward steps through
+    its tile's list front to back up to and including the entry that stops
+    it (the whole list when none does); the backward steps from the pixel's
+    last contributor back to the front.  alpha is taken in FP32 with numpy's
+    exp2 and q without fused multiply-adds, so a decision within an ulp of a
+    threshold may count one entry differently from the kernel."""
     import numpy as np
-    import oracle
-    kf = w["keyframe"]
-    okf = oracle.ingest(kf.depth, kf.rgb, fx=kf.cam.fx, cam=kf.cam.as_tuple(), pose=kf.pose)
-    out = oracle.render(oracle.ViewSpec(kf.cam.as_tuple(), w["init_pose"]), [okf])
-    contrib = int(out["n_contrib"].sum())
-    return contrib, out
+    st = plan.debug_state()
+    rec = st["records"].cpu().numpy()
+    ranges = st["ranges"].cpu().numpy().astype(np.int64)
+    ids = st["ids"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    prm = plan.prm
+    B = int(prm.tile)
+    tiles_x = (width + B - 1) // B
+    f32 = np.float32
+    amin, amax, tmin, qcut = f32(prm.alpha_min), f32(prm.alpha_max), f32(prm.t_min), f32(prm.q_cut)
+    k = f32(-0.5 * np.log2(np.e))
+    yy, xx = np.mgrid[0:B, 0:B]
+    xx, yy = xx.ravel(), yy.ravel()
+    fwd_scan = fwd_contrib = bwd_scan = 0
+    for t in range(plan.n_tiles):
+        s, e = int(ranges[t, 0]), int(ranges[t, 1])
+        px = (t % tiles_x) * B + xx
+        py = (t // tiles_x) * B + yy
+        inside = (px < width) & (py < height)
+        n = e - s
+        if n <= 0 or not inside.any():
+            continue
+        px = px[inside].astype(f32)[:, None]
+        py = py[inside].astype(f32)[:, None]
+        r = rec[ids[s:e]]
+        dx = px - r[None, :, 0]
+        dy = py - r[None, :, 1]
+        q = (r[None, :, 2] * dx) * dx + (f32(2) * r[None, :, 3] * dx) * dy + (r[None, :, 4] * dy) * dy
+        a = np.minimum(amax, r[None, :, 5] * np.exp2(q * k))
+        cover = (q <= qcut) & (a >= amin)
+        Tn = np.cumprod(np.where(cover, f32(1) - a, f32(1)), axis=1, dtype=f32)
+        stops = cover & (Tn < tmin)
+        stopped = stops.any(axis=1)
+        first = np.where(stopped, stops.argmax(axis=1), n)
+        fwd_scan += int(np.where(stopped, first + 1, n).sum())
+        took = cover & (np.arange(n)[None, :] < first[:, None])
+        nc = took.sum(axis=1)
+        fwd_contrib += int(nc.sum())
+        lastpos = np.where(nc > 0, n - 1 - took[:, ::-1].argmax(axis=1), -1)
+        bwd_scan += int((lastpos + 1).sum())
+    return dict(fwd_scanned=fwd_scan, contrib=fwd_contrib, bwd_scanned=bwd_scan)
+
+
+def lane_op_work(c):
+    """Algorithmic lane-ops of one forward and one backward launch."""
+    fwd = LANE_OPS["fwd_skip"] * (c["fwd_scanned"] - c["contrib"]) + LANE_OPS["fwd_contrib"] * c["contrib"]
+    bwd = LANE_OPS["bwd_skip"] * (c["bwd_scanned"] - c["contrib"]) + LANE_OPS["bwd_contrib"] * c["contrib"]
+    return {"composite_fwd": fwd, "composite_bwd": bwd}
 
 
 def cpu_baseline(w, seconds):
@@ -432,25 +479,44 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    contrib, _ = pair_counts(w)
-    fl = flops_per_pair()
+    # units per launch: counted at the initial pose of the frame and at the
+    # pose the timed frames end on, averaged
+    counts = []
+    for pose in (init, view.pose.clone()):
+        view.pose.copy_(pose)
+        with torch.cuda.stream(stream):
+            plan.render_fwd(stream=stream)
+        torch.cuda.synchronize()
+        counts.append(scan_counts(plan, 640, 480))
+    cnt = {key: sum(c[key] for c in counts) / len(counts) for key in counts[0]}
+    work = lane_op_work(cnt)
     roof = None
-    per = {"composite_bwd": fl["bwd_contrib"], "composite_fwd": fl["fwd_contrib"]}.get(dom)
-    if per is not None:
-        work = contrib * per
-        achieved = work / (avg[dom] * 1e-3) / 1e12
-        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_FP32_TFLOPS,
-                    unit="TFLOP/s", frac=achieved / PEAK_FP32_TFLOPS,
+    if dom in work:
+        def rate(stage):
+            return work[stage] / (avg[stage] * 1e-3) / 1e12
+        achieved = rate(dom)
+        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_LANE_OPS_T,
+                    unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS_T,
                     traffic=measured_traffic(dom),
-                    avg_ms=avg[dom], flops_per_launch=work,
-                    units="%d contributing (pixel, Gaussian) pairs x %d FLOP" % (contrib, per))
+                    avg_ms=avg[dom], lane_ops_per_launch=work[dom],
+                    units="%.0f pixel-entry steps (%.1f per pixel) of which %.0f contributing; "
+                          "%d lane-ops per entry stepped past, %d per contributor"
+                          % ((cnt["fwd_scanned"], cnt["fwd_scanned"] / (640 * 480), cnt["contrib"],
+                              LANE_OPS["fwd_skip"], LANE_OPS["fwd_contrib"])
+                             if dom == "composite_fwd" else
+                             (cnt["bwd_scanned"], cnt["bwd_scanned"] / (640 * 480), cnt["contrib"],
+                              LANE_OPS["bwd_skip"], LANE_OPS["bwd_contrib"])))
+        # the contributors alone: the method's necessary work
+        nec = cnt["contrib"] * LANE_OPS["fwd_contrib" if dom == "composite_fwd" else "bwd_contrib"]
+        roof["contributors_only"] = dict(achieved=nec / (avg[dom] * 1e-3) / 1e12,
+                                         frac=nec / (avg[dom] * 1e-3) / 1e12 / PEAK_LANE_OPS_T)
         # the other compositing kernel, same accounting
         other = "composite_bwd" if dom == "composite_fwd" else "composite_fwd"
         if avg.get(other):
-            op = fl["bwd_contrib"] if other == "composite_bwd" else fl["fwd_contrib"]
-            a2 = contrib * op / (avg[other] * 1e-3) / 1e12
-            roof[other] = dict(avg_ms=avg[other], achieved=a2, frac=a2 / PEAK_FP32_TFLOPS,
+            roof[other] = dict(avg_ms=avg[other], achieved=rate(other),
+                               frac=rate(other) / PEAK_LANE_OPS_T, lane_ops_per_launch=work[other],
                                traffic=measured_traffic(other))
+        roof["counts"] = cnt
 
     cpu = None
     if not args.no_cpu_baseline:

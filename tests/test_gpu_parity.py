@@ -482,3 +482,29 @@ def test_tile_lists_with_depth_ties(R, orc, case):
     assert same_ranges(np_(st["ranges"]), ranges)
     assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
     check_images(*imgs, orc.render(ov, [okf], margin=MARGIN), max_marginal=2e-2)
+
+
+# ----------------------------------------------------------------------------
+# the work counter behind the benchmark's roofline figure, on the GPU state
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [16, 32])
+def test_bench_work_counter_on_gpu_state(R, orc, tile):
+    """bench.py counts the compositing units from the plan's own records and
+    sorted lists; on the GPU state (bitwise equal to the oracle's, above) it
+    gives the counts it gives on the oracle's state, and its contributor
+    count agrees with the oracle's within the marginal pixels."""
+    import bench
+    from test_bench_counts import _OraclePlan
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    plan = R.Plan([gpu_kf(R, fr)], [R.View(cam.as_tuple(), vpose)], R.params(tile=tile))
+    plan.render_fwd()
+    assert plan.status()[0] == 0
+    got = bench.scan_counts(plan, cam.width, cam.height)
+    okf = oracle_kf(orc, fr)
+    ov = orc.ViewSpec(cam.as_tuple(), vpose)
+    prm = orc.params(tile=tile)
+    assert got == bench.scan_counts(_OraclePlan(orc, ov, okf, prm), cam.width, cam.height)
+    out = orc.render(ov, [okf], prm)
+    assert abs(got["contrib"] - int(out["n_contrib"].sum())) <= int(out["marginal"].sum())

@@ -4,11 +4,12 @@
 // One workgroup per (view, tile).  Each wave owns a square block of the
 // tile (8x8 pixels, or 16x16 for 32-pixel tiles with four pixels per lane).
 // The tile's depth-sorted list is walked in batches staged through LDS;
-// while staging, the block marks for every wave which entries have an
-// extent box that touches the wave's pixels (one 64-bit mask per wave and
-// 64 entries), and each wave then visits only the set bits of its masks
-// with scalar bit scans, two entries per step, recording for each lane which
-// entries reach its pixel.  The lanes then composite their own entries of a
+// while staging, the block marks for every wave which entries may reach
+// the wave's pixels -- extent box touching its block and block inside the
+// entry's cull circle (one 64-bit mask per wave and 64 entries) -- and each
+// wave then visits only the set bits of its masks with scalar bit scans,
+// four entries per step, recording for each lane which entries reach its
+// pixel (q <= q_cut, the exact test).  The lanes then composite their own entries of a
 // group of chunks (up to 256 entries) as one stream each, so a wave takes as
 // many steps as its busiest lane has entries in the whole group.
 //

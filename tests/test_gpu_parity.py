@@ -453,11 +453,13 @@ def test_long_tile_lists_bitwise(R, orc, zoom, tile):
     check_images(*imgs, ref, max_marginal=2e-2)
 
 
-@pytest.mark.parametrize("case", ["long_runs", "short_runs"])
-def test_tile_lists_with_depth_ties(R, orc, case):
+@pytest.mark.parametrize("case,tile", [("long_runs", 16), ("short_runs", 16), ("long_runs", 32)])
+def test_tile_lists_with_depth_ties(R, orc, case, tile):
     """Equal depths are ordered by id: a constant-depth back plane seen from
     its own keyframe (runs of equal depth longer than 64 entries) and a
-    keyframe whose column pairs share depths (runs of two)."""
+    keyframe whose column pairs share depths (runs of two).  At tile 32 the
+    back plane's lists exceed 768 entries (up to 1311, runs up to 983), so
+    the long-list sort takes them."""
     from paper_2506_02741_amd import synth
     if case == "long_runs":
         f, colors = synth.toy_scene(0)
@@ -469,13 +471,13 @@ def test_tile_lists_with_depth_ties(R, orc, case):
         depth[:, 1::2] = depth[:, 0::2]
         rgb, cam, pose = fr.rgb, cam_.as_tuple(), fr.pose
     k = R.Keyframe.ingest(depth, rgb, cam, pose)
-    plan = R.Plan([k], [R.View(cam, pose)], R.params(tile=16))
+    plan = R.Plan([k], [R.View(cam, pose)], R.params(tile=tile))
     imgs = plan.render_fwd()
     st = plan.debug_state()
     assert plan.status()[0] == 0
     okf = orc.ingest(depth, rgb, fx=cam[0], cam=cam, pose=pose)
     ov = orc.ViewSpec(cam, pose)
-    keys, vals, ranges = orc.tile_lists(ov, [okf], orc.params(tile=16))
+    keys, vals, ranges = orc.tile_lists(ov, [okf], orc.params(tile=tile))
     z = keys & np.uint64(0xFFFFFFFF)
     ties = sum(int(np.any(z[s + 1:e] == z[s:e - 1])) for s, e in ranges if e - s > 1)
     assert ties > 0

@@ -79,6 +79,7 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
 // `single(t)`.
 struct WaveBox {
   int bx0, by0, nx, area;
+  int src;  // a lane with a rectangle (when shared): its view is the box's
   bool shared;
 };
 
@@ -93,6 +94,7 @@ __device__ __forceinline__ WaveBox wave_box(bool has, int view, int x0, int y0, 
   const long area = vmax < 0 ? 0 : (long)b.nx * (long)(by1 - b.by0 + 1);
   b.shared = vmax >= 0 && vmin == vmax && area <= 24;
   b.area = b.shared ? (int)area : 0;
+  b.src = (int)__builtin_ctzll(ballot64(has) | (1ull << 63));
   return b;
 }
 
@@ -204,20 +206,24 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     ws.rect[r] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
     ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
   }
-  uint32_t *cnt = ws.tile_count + tile_base;
   const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
   if (box.shared) {
-    // lane j counts box tile j; one atomic instruction for the whole box
+    // lane j counts box tile j; one atomic instruction for the whole box.
+    // Lane j need not hold a record of the box's view (or any record), so
+    // the tile index takes that view's geometry from a lane that does.
+    const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);
+    const int btb = __builtin_amdgcn_readlane(tile_base, box.src);
     uint32_t mine = 0u;
     int mt = 0;
     for (int j = 0; j < box.area; j++) {
       int tx, ty;
       bool in;
       const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
-      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = ty * tiles_x + tx; }
+      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
     }
-    if (mine) atomicAdd(cnt + mt, mine);
+    if (mine) atomicAdd(ws.tile_count + mt, mine);
   } else if (has) {
+    uint32_t *cnt = ws.tile_count + tile_base;
     for (int ty = y0; ty <= y1; ty++)
       for (int tx = x0; tx <= x1; tx++) atomicAdd(cnt + ty * tiles_x + tx, 1u);
   }
@@ -290,14 +296,17 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
   const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
   if (box.shared) {
     // lane j claims the wave's slots in box tile j (all tiles in one round
-    // trip), then every tile's base is read from its owner lane
+    // trip), then every tile's base is read from its owner lane (the tile
+    // index in the box's view, whatever lane j holds)
+    const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);
+    const int btb = __builtin_amdgcn_readlane(tile_base, box.src);
     uint32_t mine = 0u;
     int mt = 0;
     for (int j = 0; j < box.area; j++) {
       int tx, ty;
       bool in;
       const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
-      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = tile_base + ty * tiles_x + tx; }
+      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
     }
     uint32_t base = 0u, lim = 0u;
     if (mine) {
@@ -368,6 +377,21 @@ __device__ __forceinline__ uint32_t wave_and_u32(uint32_t x) {
   return ((uint32_t)__builtin_amdgcn_readlane((int)x, 0) & (uint32_t)__builtin_amdgcn_readlane((int)x, 16)) &
          ((uint32_t)__builtin_amdgcn_readlane((int)x, 32) & (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
 }
+
+// Padding keys (~0) must end after every real key, but the depth passes
+// take only the depth nibbles in which the real keys differ: a real key
+// whose varying depth nibbles are all 15 (or any key, when the depth does
+// not vary) would tie with the padding on every depth pass and could keep
+// a place before it.  For such a list the top nibble is sorted as well; it
+// is below 8 in every real key (a finite positive depth), so it puts the
+// padding last.
+__device__ __forceinline__ unsigned long long nibbles_of(unsigned long long diff) {
+  unsigned long long nib = 0ull;
+#pragma unroll
+  for (int sh = 0; sh < 64; sh += 4) nib |= ((diff >> sh) & 15ull) != 0ull ? 15ull << sh : 0ull;
+  return nib;
+}
+constexpr unsigned long long kTopNibble = 15ull << 60;
 
 // Stable LSD radix passes, 4-bit digits, over the nibbles set in `digits`,
 // of the NT * E keys of a block.  Thread t holds keys t*E .. t*E+E-1 in
@@ -495,7 +519,11 @@ __device__ void block_sort_u64(unsigned long long (&k)[E], int n, unsigned long 
   unsigned long long orv = 0ull, andv = ~0ull;
 #pragma unroll
   for (int i = 0; i < NW; i++) { orv |= red[2 * i]; andv &= red[2 * i + 1]; }
-  const unsigned long long diff = orv ^ andv;
+  const unsigned long long nib = nibbles_of((orv ^ andv) & 0xFFFFFFFF00000000ull);
+  bool pad_tie = false;
+#pragma unroll
+  for (int e = 0; e < E; e++) pad_tie |= k[e] != ~0ull && (k[e] & nib) == nib;
+  const unsigned long long diff = (orv ^ andv) | (__syncthreads_or(pad_tie) ? kTopNibble : 0ull);
   radix_passes<NT, E>(k, diff & 0xFFFFFFFF00000000ull, buf, wsum, starts);
   // runs of equal depth among the first n keys, found from their first key
   bool long_run = false;
@@ -615,9 +643,14 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, ui
     alo &= in ? (uint32_t)k[e] : ~0u;
     ahi &= in ? (uint32_t)(k[e] >> 32) : ~0u;
   }
-  const unsigned long long diff =
+  const unsigned long long diff0 =
       ((unsigned long long)(wave_or_u32(ohi) ^ wave_and_u32(ahi)) << 32) |
       (wave_or_u32(olo) ^ wave_and_u32(alo));
+  const unsigned long long nib = nibbles_of(diff0 & 0xFFFFFFFF00000000ull);
+  bool pad_tie = false;
+#pragma unroll
+  for (int e = 0; e < E; e++) pad_tie |= l + kWave * e < n && (k[e] & nib) == nib;
+  const unsigned long long diff = diff0 | (ballot64(pad_tie) != 0ull ? kTopNibble : 0ull);
   if ((diff >> 32) == 0ull) {
     // one depth for the whole tile: the order is the id order
 #pragma unroll

@@ -510,3 +510,43 @@ def test_bench_work_counter_on_gpu_state(R, orc, tile):
     assert got == bench.scan_counts(_OraclePlan(orc, ov, okf, prm), cam.width, cam.height)
     out = orc.render(ov, [okf], prm)
     assert abs(got["contrib"] - int(out["n_contrib"].sum())) <= int(out["marginal"].sum())
+
+
+@pytest.mark.parametrize("case", ["one_wave", "long_list"])
+def test_tile_sort_key_with_all_varying_nibbles_15(R, orc, case):
+    """A tile whose keys differ only in nibbles where one real key holds 15
+    everywhere (depths 1.0 and 1.9999999, bits 0x3F800000 and 0x3FFFFFFF):
+    the padding of the sort must still end after that key.  'one_wave': two
+    Gaussians in one 16-pixel tile; 'long_list': a plane of 832 Gaussians at
+    depth 1.0 and one at 1.9999999 in one 32-pixel tile (a list for the
+    long-list sort)."""
+    W, H = 64, 48
+    cam = (60.0, 60.0, 32.0, 24.0, W, H)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+    near_two = np.array([0x3FFFFFFF], np.uint32).view(np.float32)[0]
+    depth = np.zeros((H, W), np.float32)
+    if case == "one_wave":
+        depth[10, 10] = 1.0
+        depth[10, 11] = near_two
+        tile = 16
+    else:
+        depth[0:26, 0:32] = 1.0
+        depth[28, 20] = near_two
+        tile = 32
+    rng = np.random.default_rng(7)
+    rgb = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    k = R.Keyframe.ingest(depth, rgb, cam, pose)
+    plan = R.Plan([k], [R.View(cam, pose)], R.params(tile=tile))
+    imgs = plan.render_fwd()
+    st = plan.debug_state()
+    assert plan.status()[0] == 0
+    okf = orc.ingest(depth, rgb, fx=cam[0], cam=cam, pose=pose)
+    ov = orc.ViewSpec(cam, pose)
+    keys, vals, ranges = orc.tile_lists(ov, [okf], orc.params(tile=tile))
+    z = (keys & np.uint64(0xFFFFFFFF)).astype(np.uint32)  # (tile << 32 | depth bits)
+    assert np.any(z == 0x3FFFFFFF)
+    if case == "long_list":
+        assert int((ranges[:, 1].astype(int) - ranges[:, 0].astype(int)).max()) > 768
+    assert same_ranges(np_(st["ranges"]), ranges)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+    check_images(*imgs, orc.render(ov, [okf], margin=MARGIN), max_marginal=2e-2)

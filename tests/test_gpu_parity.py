@@ -519,7 +519,9 @@ def test_tile_sort_key_with_all_varying_nibbles_15(R, orc, case):
     the padding of the sort must still end after that key.  'one_wave': two
     Gaussians in one 16-pixel tile; 'long_list': a plane of 832 Gaussians at
     depth 1.0 and one at 1.9999999 in one 32-pixel tile (a list for the
-    long-list sort)."""
+    long-list sort).  833 records also leave the last wave of the binning
+    with one record whose rectangle spans two tile rows, counted and placed
+    by lanes that hold no record."""
     W, H = 64, 48
     cam = (60.0, 60.0, 32.0, 24.0, W, H)
     pose = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)

@@ -552,3 +552,35 @@ def test_tile_sort_key_with_all_varying_nibbles_15(R, orc, case):
     assert same_ranges(np_(st["ranges"]), ranges)
     assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
     check_images(*imgs, orc.render(ov, [okf], margin=MARGIN), max_marginal=2e-2)
+
+
+def test_binning_wave_across_views_with_culled_owner_lanes(R, orc):
+    """Two views of one 833-Gaussian keyframe in one plan, the second turned
+    half way round (every record culled): the binning wave that holds the
+    first view's last record and the second view's first 63 shares its box
+    with lanes of the other view, which must still count and place the first
+    view's pairs in that view's tiles."""
+    W, H = 64, 48
+    cam = (60.0, 60.0, 32.0, 24.0, W, H)
+    pose = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+    away = np.concatenate([np.diag([-1.0, 1.0, -1.0]), np.zeros((3, 1))], 1).astype(np.float32)
+    depth = np.zeros((H, W), np.float32)
+    depth[0:26, 0:32] = 1.0
+    depth[28, 20] = 1.5
+    rgb = np.random.default_rng(8).uniform(0, 1, (3, H, W)).astype(np.float32)
+    k = R.Keyframe.ingest(depth, rgb, cam, pose)
+    plan = R.Plan([k], [R.View(cam, pose), R.View(cam, away)], R.params(tile=32))
+    rgb_o, dep_o, sil_o = plan.render_fwd()
+    st = plan.debug_state()
+    assert plan.status()[0] == 0
+    okf = orc.ingest(depth, rgb, fx=cam[0], cam=cam, pose=pose)
+    ov = orc.ViewSpec(cam, pose)
+    keys, vals, ranges = orc.tile_lists(ov, [okf], orc.params(tile=32))
+    nt = ranges.shape[0]
+    assert same_ranges(np_(st["ranges"])[:nt], ranges)
+    assert int(np_(st["n_pairs"])[0]) == len(vals)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+    P = W * H
+    check_images(rgb_o[:, :P], dep_o[:P], sil_o[:P], orc.render(ov, [okf], margin=MARGIN),
+                 max_marginal=2e-2)
+    assert float(sil_o[P:].abs().max()) == 0.0

@@ -10,13 +10,20 @@ retraction.  A step is one such iteration; value = 640*480*steps / seconds.
 
 Also reported on the same JSON line:
   roofline      the dominant kernel's algorithmic FP32 lane-ops per second
-                vs the VALU issue peak, its time from HIP events on the
-                stream the kernels run on
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
-                same workload
+                (its contributing (pixel, Gaussian) pairs; with every list
+                entry stepped through as a secondary figure) vs the VALU
+                issue peak, its time from HIP events on the stream the
+                kernels run on
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload,
+                single-threaded and on all the host's cores, with the host's
+                CPU model; plus bounded samples of the other workloads
   batched       mapping-section batch (5 of 8 keyframes per iteration,
                 gradients to colour/opacity/radius) in one plan vs one view
-                per launch with a host sync in between
+                per launch with a host sync in between, with the mapping
+                compositors' roofline
+  uneven        16 views of mixed resolution in one captured graph (tuned
+                tile shape) vs one view per launch
+  serving       continuous batching of Poisson render/track requests
 """
 import argparse
 import json
@@ -48,15 +55,40 @@ def tracking_setup():
     return w, k, view, plan, init
 
 
-def run_frames(plan, view, init, cfg, iters, loss):
-    """iters tracking iterations in frames of 40 from the initial pose."""
+def run_frames(plan, view, init, cfg, iters, loss, frame=40):
+    """iters tracking iterations in frames of `frame` (the last one possibly
+    shorter), each from the initial pose."""
     done = 0
     while done < iters:
-        n = min(40, iters - done)
+        n = min(frame, iters - done)
         view.pose.copy_(init)
         view.pose_adam.zero_()
         plan.track_step(cfg, n, loss[:n])
         done += n
+
+
+def frame_lengths(steps, frame):
+    """The frame lengths a run of `steps` iterations in frames of `frame` uses."""
+    return sorted({min(frame, steps - d) for d in range(0, steps, frame)}, reverse=True)
+
+
+def host_info():
+    """The host's CPU model and core counts (os.cpu_count, and the cores this
+    process may run on)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return dict(cpu_model=model, nproc=os.cpu_count(), cores_available=avail)
 
 
 # Lane-ops per unit of the compositing kernels' algorithmic work: one FP32
@@ -103,56 +135,90 @@ def measured_traffic(stage="composite_bwd"):
         return None
 
 
-def scan_counts(plan, width, height):
-    """Units the compositing launches of a one-view plan process, counted on
-    the host from the plan's own sorted tile lists and records (the state
-    the kernels read after a render): per pixel, the forward steps through
-    its tile's list front to back up to and including the entry that stops
-    it (the whole list when none does); the backward steps from the pixel's
-    last contributor back to the front.  alpha is taken in FP32 with numpy's
-    exp2 and q without fused multiply-adds, so a decision within an ulp of a
-    threshold may count one entry differently from the kernel."""
+def plan_layout(plan):
+    """(width, height, first record, first tile) of every view of a plan."""
+    layout = getattr(plan, "layout", None)
+    if layout is not None:
+        return layout
+    B = int(plan.prm.tile)
+    out, rec, tile = [], 0, 0
+    for v in plan.views:
+        w, h = v.cam.width, v.cam.height
+        out.append((w, h, rec, tile))
+        rec += sum(k.n for k in plan.keyframes[v.kf_first:v.kf_first + v.kf_count])
+        tile += ((w + B - 1) // B) * ((h + B - 1) // B)
+    return out
+
+
+def scan_counts(plan, chunk_elems=1 << 23):
+    """Units the compositing launches of a plan process, counted on the host
+    from the plan's own sorted tile lists and records (the state the kernels
+    read after a render): per pixel, the forward steps through its tile's
+    list front to back up to and including the entry that stops it (the
+    whole list when none does), and composites its contributors; the
+    backward steps from the pixel's last contributor back to the front.
+    alpha is taken in FP32 with exp2 and q without fused multiply-adds, and
+    the transmittance is a sequential FP32 product, so a decision within an
+    ulp of a threshold may count one entry differently from the kernel."""
     import numpy as np
+    import torch
     st = plan.debug_state()
-    rec = st["records"].cpu().numpy()
-    ranges = st["ranges"].cpu().numpy().astype(np.int64)
-    ids = st["ids"].cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    rec = st["records"].detach().cpu()[:, :6].contiguous()
+    ranges = st["ranges"].detach().cpu().to(torch.int64)
+    ids = st["ids"].detach().cpu().to(torch.int64) & 0xFFFFFFFF
     prm = plan.prm
     B = int(prm.tile)
-    tiles_x = (width + B - 1) // B
-    f32 = np.float32
-    amin, amax, tmin, qcut = f32(prm.alpha_min), f32(prm.alpha_max), f32(prm.t_min), f32(prm.q_cut)
-    k = f32(-0.5 * np.log2(np.e))
-    yy, xx = np.mgrid[0:B, 0:B]
-    xx, yy = xx.ravel(), yy.ravel()
-    fwd_scan = fwd_contrib = bwd_scan = 0
-    for t in range(plan.n_tiles):
-        s, e = int(ranges[t, 0]), int(ranges[t, 1])
-        px = (t % tiles_x) * B + xx
-        py = (t // tiles_x) * B + yy
-        inside = (px < width) & (py < height)
-        n = e - s
-        if n <= 0 or not inside.any():
-            continue
-        px = px[inside].astype(f32)[:, None]
-        py = py[inside].astype(f32)[:, None]
-        r = rec[ids[s:e]]
-        dx = px - r[None, :, 0]
-        dy = py - r[None, :, 1]
-        q = (r[None, :, 2] * dx) * dx + (f32(2) * r[None, :, 3] * dx) * dy + (r[None, :, 4] * dy) * dy
-        a = np.minimum(amax, r[None, :, 5] * np.exp2(q * k))
-        cover = (q <= qcut) & (a >= amin)
-        Tn = np.cumprod(np.where(cover, f32(1) - a, f32(1)), axis=1, dtype=f32)
-        stops = cover & (Tn < tmin)
-        stopped = stops.any(axis=1)
-        first = np.where(stopped, stops.argmax(axis=1), n)
-        fwd_scan += int(np.where(stopped, first + 1, n).sum())
-        took = cover & (np.arange(n)[None, :] < first[:, None])
-        nc = took.sum(axis=1)
-        fwd_contrib += int(nc.sum())
-        lastpos = np.where(nc > 0, n - 1 - took[:, ::-1].argmax(axis=1), -1)
-        bwd_scan += int((lastpos + 1).sum())
-    return dict(fwd_scanned=fwd_scan, contrib=fwd_contrib, bwd_scanned=bwd_scan)
+    f32 = torch.float32
+    amin, amax = float(np.float32(prm.alpha_min)), float(np.float32(prm.alpha_max))
+    tmin, qcut = float(np.float32(prm.t_min)), float(np.float32(prm.q_cut))
+    k = float(np.float32(-0.5 * np.log2(np.e)))
+    yy, xx = torch.meshgrid(torch.arange(B), torch.arange(B), indexing="ij")
+    xx, yy = xx.reshape(-1), yy.reshape(-1)
+    tot = dict(fwd_scanned=0, contrib=0, bwd_scanned=0)
+    for (W, H, rb, tb) in plan_layout(plan):
+        tiles_x, tiles_y = (W + B - 1) // B, (H + B - 1) // B
+        nt_view = tiles_x * tiles_y
+        lens = (ranges[tb:tb + nt_view, 1] - ranges[tb:tb + nt_view, 0]).clamp(min=0)
+        order = torch.argsort(lens, stable=True)   # similar lengths share a chunk
+        i = 0
+        while i < nt_view:
+            L = max(int(lens[order[min(nt_view - 1, i)]]), 1)
+            j = i + 1
+            while j < nt_view and int(lens[order[j]]) <= L * 2 and (j - i + 1) * B * B * max(
+                    int(lens[order[j]]), 1) <= chunk_elems:
+                j += 1
+            t = order[i:j]
+            L = max(int(lens[t].max()), 1)
+            i = j
+            s0 = ranges[tb + t, 0]
+            n = lens[t]
+            pos = s0[:, None] + torch.arange(L)[None, :]
+            valid = torch.arange(L)[None, :] < n[:, None]
+            rows = rb + ids[torch.where(valid, pos, s0[:, None]).clamp(max=ids.numel() - 1)]
+            r = rec[rows]                                    # [nt, L, 6]
+            px = ((t % tiles_x) * B)[:, None] + xx[None, :]  # [nt, B*B]
+            py = ((t // tiles_x) * B)[:, None] + yy[None, :]
+            inside = (px < W) & (py < H)
+            dx = px.to(f32)[:, :, None] - r[:, None, :, 0]
+            dy = py.to(f32)[:, :, None] - r[:, None, :, 1]
+            q = (r[:, None, :, 2] * dx) * dx + ((2.0 * r[:, None, :, 3]) * dx) * dy \
+                + (r[:, None, :, 4] * dy) * dy
+            a = torch.clamp(r[:, None, :, 5] * torch.exp2(q * k), max=amax)
+            cover = (q <= qcut) & (a >= amin) & valid[:, None, :]
+            del dx, dy, q
+            Tn = torch.cumprod(torch.where(cover, 1.0 - a, torch.ones_like(a)), dim=2)
+            stops = cover & (Tn < tmin)
+            stopped = stops.any(dim=2)
+            nn = n[:, None].expand_as(stopped)
+            first = torch.where(stopped, stops.to(torch.int8).argmax(dim=2), nn)
+            tot["fwd_scanned"] += int(torch.where(stopped, first + 1, nn)[inside].sum())
+            took = cover & (torch.arange(L)[None, None, :] < first[:, :, None])
+            nc = took.sum(dim=2)
+            tot["contrib"] += int(nc[inside].sum())
+            lastpos = torch.where(nc > 0, L - 1 - took.flip(2).to(torch.int8).argmax(dim=2),
+                                  torch.full_like(nc, -1))
+            tot["bwd_scanned"] += int((lastpos + 1)[inside].sum())
+    return tot
 
 
 def lane_op_work(c):
@@ -162,7 +228,28 @@ def lane_op_work(c):
     return {"composite_fwd": fwd, "composite_bwd": bwd}
 
 
-def cpu_baseline(w, seconds):
+def compositing_roofline(cnt, stage_ms):
+    """Per compositing kernel: the contributors' lane-ops per second (the
+    method's necessary work, the headline) and the lane-ops of every list
+    entry the pixels step through, each against the VALU issue peak."""
+    work = lane_op_work(cnt)
+    out = {}
+    for stage, key in (("composite_fwd", "fwd_contrib"), ("composite_bwd", "bwd_contrib")):
+        ms = stage_ms.get(stage)
+        if not ms:
+            continue
+        nec = cnt["contrib"] * LANE_OPS[key]
+        out[stage] = dict(avg_ms=ms, contrib_lane_ops=nec,
+                          achieved=nec / (ms * 1e-3) / 1e12,
+                          frac=nec / (ms * 1e-3) / 1e12 / PEAK_LANE_OPS_T,
+                          with_list_steps=dict(lane_ops=work[stage],
+                                               achieved=work[stage] / (ms * 1e-3) / 1e12,
+                                               frac=work[stage] / (ms * 1e-3) / 1e12 / PEAK_LANE_OPS_T))
+    return out
+
+
+def cpu_tracking_iterations(w, seconds, threads):
+    """Oracle tracking iterations of the 640x480 frame for about `seconds`."""
     import numpy as np
     import oracle
     kf = w["keyframe"]
@@ -170,18 +257,97 @@ def cpu_baseline(w, seconds):
     pose = np.asarray(w["init_pose"], np.float32)
     st = dict(m=np.zeros(6), v=np.zeros(6), t=0)
     n = 0
-    t0 = time.perf_counter()
-    while True:
-        view = oracle.ViewSpec(kf.cam.as_tuple(), pose)
-        L, new_pose, st, g, _ = oracle.track_iteration(view, [okf], kf.rgb, kf.depth, st)
-        pose = new_pose.astype(np.float32)
-        n += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=640 * 480 * n / dt / 1e6, unit="Mpix/s", cores=1, kind="oracle",
-                sample="%d tracking iterations (fwd + Eq.1 + bwd to twist + Adam/retraction) of "
-                       "the 640x480 frame, single-threaded, %.1f s" % (n, dt))
+    with oracle.threads(threads):
+        t0 = time.perf_counter()
+        while True:
+            view = oracle.ViewSpec(kf.cam.as_tuple(), pose)
+            L, new_pose, st, g, _ = oracle.track_iteration(view, [okf], kf.rgb, kf.depth, st)
+            pose = new_pose.astype(np.float32)
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+    return n, dt
+
+
+def cpu_baseline(w, seconds, all_seconds):
+    """The oracle on the host: single-threaded (the parity reference) and its
+    OpenMP build on every available core, on the tracking workload."""
+    info = host_info()
+    n, dt = cpu_tracking_iterations(w, seconds, 1)
+    out = dict(value=640 * 480 * n / dt / 1e6, unit="Mpix/s", cores=1, kind="oracle",
+               sample="%d tracking iterations (fwd + Eq.1 + bwd to twist + Adam/retraction) of "
+                      "the 640x480 frame, single-threaded, %.1f s" % (n, dt), **info)
+    if all_seconds > 0 and info["cores_available"] > 1:
+        c = info["cores_available"]
+        n2, dt2 = cpu_tracking_iterations(w, all_seconds, c)
+        out["all_cores"] = dict(value=640 * 480 * n2 / dt2 / 1e6, unit="Mpix/s", cores=c,
+                                sample="%d tracking iterations, OpenMP on %d threads, %.1f s"
+                                       % (n2, c, dt2))
+    return out
+
+
+def cpu_configs(section, uneven_frames, uneven_views, threads):
+    """Oracle fwd+bwd timings beside the other workloads (bounded samples):
+    the 64x48 toy view whole (L1 colour + L1 depth against a jittered-colour
+    target); one view of the mapping section (Eq. 2, 8 keyframes); one view
+    of each resolution of the uneven batch (over its 8-keyframe section)."""
+    import numpy as np
+    import oracle
+    from paper_2506_02741_amd import synth
+    res = {}
+
+    def fwd_bwd(view, kfs, target, eq2):
+        t0 = time.perf_counter()
+        out = oracle.render(view, kfs)
+        H, W = int(view.cam[5]), int(view.cam[4])
+        if eq2:
+            L, g_rgb, g_d = oracle.map_loss(H, W, out["rgb"], out["depth"], target[0], target[1])
+        else:
+            g_rgb = -np.sign(target[0].reshape(3, -1) - out["rgb"])
+            g_d = -np.sign(target[1].reshape(-1) - out["depth"])
+        oracle.render_bwd(view, kfs, g_rgb, g_d, None)
+        return time.perf_counter() - t0
+
+    f, colors = synth.toy_scene(0)
+    cam = f.cam.as_tuple()
+    okf = oracle.ingest(f.depth, colors, fx=f.cam.fx, cam=cam, pose=f.pose)
+    rng = np.random.default_rng(0)
+    tgt = np.clip(colors + rng.uniform(-0.1, 0.1, colors.shape), 0, 1).astype(np.float32)
+    ov = oracle.ViewSpec(cam, f.pose)
+    for th in (1, threads):
+        with oracle.threads(th):
+            dt = min(fwd_bwd(ov, [okf], (tgt, f.depth), False) for _ in range(3))
+        res["toy_64x48_threads%d" % th] = dict(mpix_s=64 * 48 / dt / 1e6, seconds=dt)
+    if section is not None:
+        frames = section
+        okfs = [oracle.ingest(fr.depth, fr.rgb, fx=fr.cam.fx, cam=fr.cam.as_tuple(), pose=fr.pose)
+                for fr in frames]
+        fr = frames[3]
+        v = oracle.ViewSpec(fr.cam.as_tuple(), fr.pose, 0, len(frames))
+        with oracle.threads(threads):
+            dt = fwd_bwd(v, okfs, (fr.rgb, fr.depth), True)
+        res["mapping_view_640x480_8kf_threads%d" % threads] = dict(
+            mpix_s=640 * 480 / dt / 1e6, seconds=dt,
+            sample="one view of the 5-view mapping iteration (fwd + Eq. 2 + bwd)")
+    if uneven_frames is not None:
+        done = set()
+        for vi in uneven_views:
+            fr = uneven_frames[vi]
+            wh = (fr.cam.width, fr.cam.height)
+            if wh in done:
+                continue
+            done.add(wh)
+            first = 8 * (vi // 8)
+            sec = uneven_frames[first:first + 8]
+            okfs = [oracle.ingest(x.depth, x.rgb, fx=x.cam.fx, cam=x.cam.as_tuple(), pose=x.pose)
+                    for x in sec]
+            v = oracle.ViewSpec(fr.cam.as_tuple(), fr.pose, 0, 8)
+            with oracle.threads(threads):
+                dt = fwd_bwd(v, okfs, (fr.rgb, fr.depth), True)
+            res["uneven_view_%dx%d_threads%d" % (wh[0], wh[1], threads)] = dict(
+                mpix_s=wh[0] * wh[1] / dt / 1e6, seconds=dt)
+    return res
 
 
 def batched_vs_single(iters):
@@ -223,6 +389,9 @@ def batched_vs_single(iters):
     p.render_bwd(g, None, None, twist=False)
     bstages = {s: v[0] for s, v in p.timing(False).items()}
     pairs = int(p.debug_state()["n_pairs"].item())
+    # the units of that last batch's compositing launches and their rates
+    cnt = scan_counts(p)
+    roof = compositing_roofline(cnt, bstages)
     del plans, first, p
     # one view per launch
     singles = {i: R.Plan(ks, views_of([i])) for i in range(8)}
@@ -243,7 +412,8 @@ def batched_vs_single(iters):
     return dict(workload="mapping section: 8 keyframes 640x480 (2,457,600 Gaussians), 5 views "
                          "per iteration, fwd+bwd to colour/opacity/radius",
                 iters=iters, batched_mpix_s=px / tb / 1e6, one_view_per_launch_mpix_s=px / ts / 1e6,
-                speedup=ts / tb, batched_stages_ms=bstages, pairs=pairs)
+                speedup=ts / tb, batched_stages_ms=bstages, pairs=pairs, roofline=roof,
+                counts=cnt), frames
 
 
 def uneven_run(reps):
@@ -317,7 +487,7 @@ def uneven_run(reps):
                 map_gaussians=n_gauss, pixels=px, tuned=dict(tile=entry["tile"], batch=entry["batch"]),
                 sweep_ms=entry["sweep"], graph_mpix_s=px / tuned_s / 1e6,
                 default_shape_mpix_s=px / default_s / 1e6, one_view_per_launch_mpix_s=px / single_s / 1e6,
-                speedup=single_s / tuned_s, generation_s=gen_s)
+                speedup=single_s / tuned_s, generation_s=gen_s), frames, list(w["views"])
 
 
 def serving_run(seconds, rate, n_sections, budget_gib, seed=4, low_rate=0.0):
@@ -404,7 +574,9 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-all-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-configs", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-iters", type=int, default=20)
     ap.add_argument("--no-serving", action="store_true")
@@ -433,14 +605,25 @@ def main():
     log("bench: building tracking workload (640x480, 307,200 Gaussians)")
     w, k, view, plan, init = tracking_setup()
     cfg = R.track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002)
-    loss = torch.zeros(40, 1, device="cuda")
-    # a non-default stream: each 40-iteration frame is one replay of a
-    # captured graph of the iteration's kernels
+    # frames of up to 40 iterations; a non-default stream, so that each frame
+    # length is one replay of a captured graph of the iteration's kernels.
+    # The warmup runs every frame length the timed region uses (at least one
+    # frame each, at least `warmup` iterations), so no graph is captured
+    # while timing.
+    frame = max(1, min(40, args.steps))
+    loss = torch.zeros(frame, 1, device="cuda")
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    log("bench: warmup %d iterations" % args.warmup)
+    lens = frame_lengths(args.steps, frame)
+    warm = 0
     with torch.cuda.stream(stream):
-        run_frames(plan, view, init, cfg, args.warmup, loss)
+        for n in lens:
+            run_frames(plan, view, init, cfg, n, loss, frame)
+            warm += n
+        while warm < args.warmup:
+            run_frames(plan, view, init, cfg, frame, loss, frame)
+            warm += frame
+    log("bench: warmup %d iterations (frames of %s)" % (warm, lens))
     torch.cuda.synchronize()
     rc, need = plan.status(stream=stream)
     if rc != 0:
@@ -450,7 +633,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
-        run_frames(plan, view, init, cfg, args.steps, loss)
+        run_frames(plan, view, init, cfg, args.steps, loss, frame)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     rc, need = plan.status(stream=stream)
@@ -464,7 +647,7 @@ def main():
     log("bench: stage timing")
     plan.timing(True, repeat=10)
     with torch.cuda.stream(stream):
-        run_frames(plan, view, init, cfg, 80, loss)
+        run_frames(plan, view, init, cfg, 2 * frame, loss, frame)
     stages = plan.timing(False)
     avg = {s: ms / n for s, (ms, n) in stages.items()}
     dom = max(stages, key=lambda s: stages[s][0])
@@ -486,51 +669,40 @@ def main():
         with torch.cuda.stream(stream):
             plan.render_fwd(stream=stream)
         torch.cuda.synchronize()
-        counts.append(scan_counts(plan, 640, 480))
+        counts.append(scan_counts(plan))
     cnt = {key: sum(c[key] for c in counts) / len(counts) for key in counts[0]}
-    work = lane_op_work(cnt)
+    comp = compositing_roofline(cnt, avg)
     roof = None
-    if dom in work:
-        def rate(stage):
-            return work[stage] / (avg[stage] * 1e-3) / 1e12
-        achieved = rate(dom)
-        roof = dict(kernel=dom, bound="alu", achieved=achieved, peak=PEAK_LANE_OPS_T,
-                    unit="Tlane-op/s", frac=achieved / PEAK_LANE_OPS_T,
-                    traffic=measured_traffic(dom),
-                    avg_ms=avg[dom], lane_ops_per_launch=work[dom],
-                    units="%.0f pixel-entry steps (%.1f per pixel) of which %.0f contributing; "
-                          "%d lane-ops per entry stepped past, %d per contributor"
-                          % ((cnt["fwd_scanned"], cnt["fwd_scanned"] / (640 * 480), cnt["contrib"],
-                              LANE_OPS["fwd_skip"], LANE_OPS["fwd_contrib"])
-                             if dom == "composite_fwd" else
-                             (cnt["bwd_scanned"], cnt["bwd_scanned"] / (640 * 480), cnt["contrib"],
-                              LANE_OPS["bwd_skip"], LANE_OPS["bwd_contrib"])))
-        # the contributors alone: the method's necessary work
-        nec = cnt["contrib"] * LANE_OPS["fwd_contrib" if dom == "composite_fwd" else "bwd_contrib"]
-        roof["contributors_only"] = dict(achieved=nec / (avg[dom] * 1e-3) / 1e12,
-                                         frac=nec / (avg[dom] * 1e-3) / 1e12 / PEAK_LANE_OPS_T)
-        # the other compositing kernel, same accounting
+    if dom in comp:
+        d = comp[dom]
+        per = LANE_OPS["fwd_contrib" if dom == "composite_fwd" else "bwd_contrib"]
+        roof = dict(kernel=dom, bound="alu", achieved=d["achieved"], peak=PEAK_LANE_OPS_T,
+                    unit="Tlane-op/s", frac=d["frac"], traffic=measured_traffic(dom),
+                    avg_ms=d["avg_ms"], lane_ops_per_launch=d["contrib_lane_ops"],
+                    units="%.0f contributing (pixel, Gaussian) pairs per launch (%.1f per pixel), "
+                          "%d lane-ops each" % (cnt["contrib"], cnt["contrib"] / (640 * 480), per),
+                    with_list_steps=dict(d["with_list_steps"], units=(
+                        "%.0f pixel-entry steps (%.1f per pixel) of which %.0f contributing; "
+                        "%d lane-ops per entry stepped past, %d per contributor"
+                        % ((cnt["fwd_scanned"], cnt["fwd_scanned"] / (640 * 480), cnt["contrib"],
+                            LANE_OPS["fwd_skip"], LANE_OPS["fwd_contrib"])
+                           if dom == "composite_fwd" else
+                           (cnt["bwd_scanned"], cnt["bwd_scanned"] / (640 * 480), cnt["contrib"],
+                            LANE_OPS["bwd_skip"], LANE_OPS["bwd_contrib"])))))
         other = "composite_bwd" if dom == "composite_fwd" else "composite_fwd"
-        if avg.get(other):
-            roof[other] = dict(avg_ms=avg[other], achieved=rate(other),
-                               frac=rate(other) / PEAK_LANE_OPS_T, lane_ops_per_launch=work[other],
-                               traffic=measured_traffic(other))
+        if other in comp:
+            roof[other] = dict(comp[other], traffic=measured_traffic(other))
         roof["counts"] = cnt
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("bench: CPU oracle baseline (~%.0f s)" % args.cpu_seconds)
-        cpu = cpu_baseline(w, args.cpu_seconds)
-
-    batched = None
+    batched = section_frames = None
     if not args.no_batched:
         log("bench: batched vs one view per launch")
-        batched = batched_vs_single(args.batched_iters)
+        batched, section_frames = batched_vs_single(args.batched_iters)
 
-    uneven = None
+    uneven = uneven_frames = uneven_views = None
     if not args.no_uneven:
         log("bench: uneven 16-view batch with autotuned tiles")
-        uneven = uneven_run(args.uneven_reps)
+        uneven, uneven_frames, uneven_views = uneven_run(args.uneven_reps)
 
     serving = None
     if not args.no_serving:
@@ -538,13 +710,24 @@ def main():
         serving = serving_run(args.serve_seconds, args.serve_rate, args.serve_sections,
                               args.serve_budget_gib, low_rate=args.serve_rate_low)
 
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline (~%.0f s single-threaded, ~%.0f s all cores)"
+            % (args.cpu_seconds, args.cpu_all_seconds))
+        cpu = cpu_baseline(w, args.cpu_seconds, args.cpu_all_seconds)
+        if not args.no_cpu_configs:
+            log("bench: CPU oracle on the other workloads (bounded samples)")
+            cpu["other_workloads"] = cpu_configs(section_frames, uneven_frames, uneven_views,
+                                                 cpu["cores_available"])
+
     out = dict(metric="fwd+bwd Mpix/s at 640x480 vs 1-view/launch; p50/p99 render-request latency",
                value=value, unit="Mpix/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=dt * 1e3 / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                data="synthetic",
                config=dict(workload="tracking 640x480: 1 keyframe, 307,200 view-tied Gaussians, "
-                                    "40-iteration frames of fwd + Eq.1 + bwd to twist + pose step",
+                                    "%d-iteration frames of fwd + Eq.1 + bwd to twist + pose step"
+                                    % frame,
                            global_batch=1, seq_len=0, parallelism="none"),
                roofline=roof, cpu_baseline=cpu, stages_ms=avg, batched=batched, uneven=uneven,
                serving=serving)

@@ -152,7 +152,8 @@ int vtgs_ingest_fill(const float *depth_img, const float *rgb_img, const uint8_t
  * the descriptors, device pointers inside are borrowed and must stay valid
  * while the plan is used) and the room for (Gaussian, tile) pairs.
  * pair_capacity <= 0 picks ceil(1.5 (1 + 10/tile)^2) pairs per (view,
- * Gaussian) record plus 65536.  The caller
+ * Gaussian) record plus 65536, at most 2^31 - 1; an explicit pair_capacity
+ * above 2^31 - 1 is VTGS_E_ARG (tile lists use 32-bit positions).  The caller
  * allocates vtgs_plan_workspace_bytes() bytes of device memory (256-byte
  * aligned) and binds it once with vtgs_plan_bind(), which uploads the
  * descriptors on `stream`.  A plan is used by one host thread at a time.
@@ -233,6 +234,20 @@ int vtgs_plan_timing(vtgs_plan *plan, int32_t enable, double *ms, int64_t *count
  * int64) the pairs of the last render.  Any pointer may be NULL. */
 int vtgs_debug_state(vtgs_plan *plan, float *records, int32_t *rect, uint32_t *ranges,
                      uint32_t *ids, int64_t *n_pairs, void *stream);
+
+/* Copies, on `stream`, of the plan's internal images (device [5][P]: RGB,
+ * depth, silhouette of the last forward that track_step or map_step ran)
+ * and of the upstream gradients map_step formed from Eq. 2 (device [5][P]:
+ * dLoss/dRGB, dLoss/ddepth, and a zero silhouette plane) [Sec. 3.4].
+ * Either pointer may be NULL. */
+int vtgs_debug_images(vtgs_plan *plan, float *img, float *gimg, void *stream);
+
+/* Adds, on `stream`, the per-Gaussian gradients (colour, opacity, radius)
+ * that the last backward to colour/opacity/radius left in the workspace --
+ * the values map_step's Adam step used -- into g_color, g_opacity and
+ * g_radius of every learnable keyframe that has them.  VTGS_E_ARG when the
+ * plan has no learnable keyframe or no such backward ran on it yet. */
+int vtgs_debug_gather(vtgs_plan *plan, void *stream);
 
 #ifdef __cplusplus
 }

@@ -22,14 +22,23 @@ DEFAULTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, q_cut=11.0826
                 z_near=0.01, lowpass=0.3, bg=(0.0, 0.0, 0.0), tile=16)
 
 
+SO_OMP = os.path.join(HERE, "liboracle_omp.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall"]
+
+
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc -O2 -ffp-contract=off (no fast-math)."""
+    """Compile oracle.c with gcc -O2 -ffp-contract=off (no fast-math): the
+    single-threaded reference, and the same source with OpenMP for the
+    all-cores timing."""
     src = os.path.join(HERE, "oracle.c")
-    if force or not os.path.exists(SO) or os.path.getmtime(SO) < os.path.getmtime(src):
-        tmp = SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
-                               "-Wall", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
-        os.replace(tmp, SO)
+    hdr = os.path.join(HERE, "oracle.h")
+    newest = max(os.path.getmtime(src), os.path.getmtime(hdr))
+    for so, extra in ((SO, []), (SO_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(so) or os.path.getmtime(so) < newest:
+            tmp = so + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc"] + CFLAGS + extra + ["-shared", "-fPIC", "-o", tmp, src,
+                                                               "-lm"])
+            os.replace(tmp, so)
     return SO
 
 
@@ -72,14 +81,35 @@ class Values(C.Structure):
                 ("twist", C.c_double * 6), ("geometry64", C.c_int32)]
 
 
-_lib = None
+_libs = {}
+_threads = [1]
+
+
+class threads:
+    """Within ``with oracle.threads(n):`` (n > 1) the oracle runs its OpenMP
+    build on n threads; otherwise the single-threaded reference."""
+
+    def __init__(self, n):
+        self.n = int(n)
+
+    def __enter__(self):
+        self.prev = _threads[0]
+        _threads[0] = self.n
+        if self.n > 1:
+            lib().omp_set_num_threads(self.n)
+        return self
+
+    def __exit__(self, *exc):
+        _threads[0] = self.prev
 
 
 def lib():
-    global _lib
-    if _lib is None:
+    key = "omp" if _threads[0] > 1 else "serial"
+    if key not in _libs:
         build()
-        L = C.CDLL(SO)
+        L = C.CDLL(SO_OMP if key == "omp" else SO)
+        if key == "omp":
+            L.omp_set_num_threads.argtypes = [C.c_int]
         P = C.c_void_p
         L.orc_ingest_count.restype = C.c_int32
         L.orc_ingest_count.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
@@ -108,8 +138,8 @@ def lib():
         L.orc_se3_exp.argtypes = [P, P]
         L.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int64, C.c_double, C.c_double,
                                C.c_double, C.c_double]
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _p(a):
@@ -384,6 +414,6 @@ def track_iteration(view, kfs, obs_rgb, obs_depth, state, alpha=0.5, beta=1.0, l
     return L, new_pose, dict(m=m, v=v, t=t), g, out
 
 
-__all__ = ["DEFAULTS", "Keyframe", "ViewSpec", "params", "ingest", "relpose32", "preprocess32",
+__all__ = ["DEFAULTS", "threads", "Keyframe", "ViewSpec", "params", "ingest", "relpose32", "preprocess32",
            "tile_lists", "slice_size", "render", "render_bwd", "track_loss", "ssim", "map_loss",
            "se3_exp", "adam", "compose", "track_iteration", "REC_DTYPE"]

@@ -15,6 +15,12 @@
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.
  * The FP32 decision path relies on IEEE single arithmetic with no
  * contraction; every value and gradient is then evaluated in FP64.
+ * The same source built with -fopenmp (the all-cores timing of the CPU
+ * baseline) splits the per-pixel loops over threads: the forward's pixels
+ * are independent (its output is bitwise the single-threaded one); the
+ * backward gives each thread a contiguous range of rows with its own
+ * gradient sums, added in row order.  Without OpenMP there is one range and
+ * the sums run in pixel order.
  *
  * Parity pins: see tests/test_oracle_*.py (closed forms, invariants,
  * brute force, finite differences, library SSIM).
@@ -25,6 +31,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ------------------------------------------------------------------------ */
 /* keyframe ingestion (Sec. 3.2: a Gaussian at every pixel with valid depth; */
@@ -435,6 +444,12 @@ static int lists_build(const orc_view *v, const orc_kf *kfs, const orc_params *p
       if (!L->e || !fill) { free(fill); return -1; }
       for (int64_t p = 0; p < P; p++) fill[p] = L->off[p];
     }
+    /* (threads claim list slots with atomics; each pixel's list is sorted by
+     * its unique (depth, id) keys below, so the order of claims is immaterial) */
+    int64_t viol = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : viol)
+#endif
     for (int32_t g = 0; g < s->N; g++) {
       const orc_rec *r = &s->rec[g];
       if (!r->count) continue;
@@ -454,20 +469,31 @@ static int lists_build(const orc_view *v, const orc_kf *kfs, const orc_params *p
           if (pass == 0) {
             if (mg) L->marg[p] = 1;
             if (ok) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
               L->off[p + 1]++;
-              if (fabsf((float)x - r->mx) > r->ext || fabsf((float)y - r->my) > r->ext)
-                L->superset_violations++;
+              if (fabsf((float)x - r->mx) > r->ext || fabsf((float)y - r->my) > r->ext) viol++;
             }
           } else if (ok) {
-            ent *e = &L->e[fill[p]++];
+            int64_t slot;
+#ifdef _OPENMP
+#pragma omp atomic capture
+#endif
+            slot = fill[p]++;
+            ent *e = &L->e[slot];
             e->zb = fbits(r->pz);
             e->id = g;
             e->clamped = cl;
           }
         }
     }
+    if (pass == 0) L->superset_violations = viol;
     free(fill);
   }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024)
+#endif
   for (int64_t p = 0; p < P; p++)
     qsort(L->e + L->off[p], (size_t)(L->off[p + 1] - L->off[p]), sizeof(ent), cmp_ent);
   return 0;
@@ -545,6 +571,9 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
     lists_t L;
     if (lists_build(v, kfs, prm, &s, margin, &L)) { lists_free(&L); scene_free(&s); return -1; }
     rc = L.superset_violations ? 1 : 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
     for (int64_t p = 0; p < P; p++) {
       double C[3], D, T;
       uint8_t mg = L.marg[p];
@@ -585,33 +614,46 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
 /* S = 1 - T_N, with T_i = prod_{j<i} (1 - a_j), contributor sets fixed.     */
 /* ------------------------------------------------------------------------ */
 
-int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
-                   const orc_values *val, const double *g_rgb, const double *g_depth,
-                   const double *g_sil, double *g_color, double *g_opac, double *g_rad,
-                   double *g_twist, double *g_mag) {
-  scene_t s;
-  if (scene_build(v, kfs, prm, val, &s)) return -1;
-  lists_t L;
-  if (lists_build(v, kfs, prm, &s, 0.f, &L)) { lists_free(&L); scene_free(&s); return -1; }
+/* Per-thread partial sums of the backward: the pixels of a contiguous range
+ * of rows add their terms here; the ranges are reduced in row order. */
+typedef struct {
+  double *g_color, *g_opac, *g_rad, *g_p, *mag, *mag_p;
+} bwd_acc;
+
+static int bwd_acc_init(bwd_acc *b, int32_t N, int want_mag) {
+  size_t n1 = (size_t)(N > 0 ? N : 1);
+  memset(b, 0, sizeof(*b));
+  b->g_color = (double *)calloc(3 * n1, sizeof(double));
+  b->g_opac = (double *)calloc(n1, sizeof(double));
+  b->g_rad = (double *)calloc(n1, sizeof(double));
+  b->g_p = (double *)calloc(3 * n1, sizeof(double));
+  if (want_mag) {
+    b->mag = (double *)calloc(5 * n1, sizeof(double));
+    b->mag_p = (double *)calloc(3 * n1, sizeof(double));
+  }
+  return b->g_color && b->g_opac && b->g_rad && b->g_p && (!want_mag || (b->mag && b->mag_p)) ? 0 : -1;
+}
+
+static void bwd_acc_free(bwd_acc *b) {
+  free(b->g_color); free(b->g_opac); free(b->g_rad); free(b->g_p); free(b->mag); free(b->mag_p);
+}
+
+/* The backward terms of the pixels [p0, p1). */
+static void bwd_pixels(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
+                       const scene_t *sp, const lists_t *Lp, int64_t p0, int64_t p1, int64_t maxn,
+                       const double *g_rgb, const double *g_depth, const double *g_sil,
+                       bwd_acc *acc) {
+  const scene_t s = *sp;
+  const lists_t L = *Lp;
   int32_t N = s.N, W = v->cam.width;
   int64_t P = (int64_t)W * v->cam.height;
-  double *g_p = (double *)calloc((size_t)(N > 0 ? N : 1) * 3, sizeof(double));
-  memset(g_color, 0, sizeof(double) * 3 * (size_t)N);
-  memset(g_opac, 0, sizeof(double) * (size_t)N);
-  memset(g_rad, 0, sizeof(double) * (size_t)N);
-  double *mag_p = NULL;
-  if (g_mag) {
-    memset(g_mag, 0, sizeof(double) * (5 * (size_t)N + 6));
-    mag_p = (double *)calloc((size_t)(N > 0 ? N : 1) * 3, sizeof(double));
-  }
-  int64_t maxn = 0;
-  for (int64_t p = 0; p < P; p++)
-    if (L.off[p + 1] - L.off[p] > maxn) maxn = L.off[p + 1] - L.off[p];
+  double *g_color = acc->g_color, *g_opac = acc->g_opac, *g_rad = acc->g_rad, *g_p = acc->g_p;
+  double *g_mag = acc->mag, *mag_p = acc->mag_p;
   double *a = (double *)malloc(sizeof(double) * (size_t)(maxn + 1));
   double *G = (double *)malloc(sizeof(double) * (size_t)(maxn + 1));
   double *T = (double *)malloc(sizeof(double) * (size_t)(maxn + 2));
   double *qw = (double *)malloc(sizeof(double) * 2 * (size_t)(maxn + 1));
-  for (int64_t p = 0; p < P; p++) {
+  for (int64_t p = p0; p < p1; p++) {
     int32_t x = (int32_t)(p % W), y = (int32_t)(p / W);
     const ent *e = L.e + L.off[p];
     int64_t n = L.off[p + 1] - L.off[p];
@@ -683,6 +725,64 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
       }
     }
   }
+  free(a); free(G); free(T); free(qw);
+}
+
+int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
+                   const orc_values *val, const double *g_rgb, const double *g_depth,
+                   const double *g_sil, double *g_color, double *g_opac, double *g_rad,
+                   double *g_twist, double *g_mag) {
+  scene_t s;
+  if (scene_build(v, kfs, prm, val, &s)) return -1;
+  lists_t L;
+  if (lists_build(v, kfs, prm, &s, 0.f, &L)) { lists_free(&L); scene_free(&s); return -1; }
+  int32_t N = s.N, W = v->cam.width, H = v->cam.height;
+  int64_t P = (int64_t)W * H;
+  int64_t maxn = 0;
+  for (int64_t p = 0; p < P; p++)
+    if (L.off[p + 1] - L.off[p] > maxn) maxn = L.off[p + 1] - L.off[p];
+  /* rows split into one contiguous range per thread (one range without
+   * OpenMP); every range sums into its own buffers */
+  int nt = 1;
+#ifdef _OPENMP
+  nt = omp_get_max_threads();
+  if (nt > H) nt = H > 0 ? H : 1;
+#endif
+  bwd_acc *acc = (bwd_acc *)calloc((size_t)nt, sizeof(bwd_acc));
+  int bad = acc == NULL;
+  for (int t = 0; t < nt && !bad; t++) bad |= bwd_acc_init(&acc[t], N, g_mag != NULL);
+  if (bad) {
+    if (acc) for (int t = 0; t < nt; t++) bwd_acc_free(&acc[t]);
+    free(acc); lists_free(&L); scene_free(&s);
+    return -1;
+  }
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(static, 1)
+#endif
+  for (int t = 0; t < nt; t++) {
+    int64_t r0 = (int64_t)H * t / nt, r1 = (int64_t)H * (t + 1) / nt;
+    bwd_pixels(v, kfs, prm, &s, &L, r0 * W, r1 * W, maxn, g_rgb, g_depth, g_sil, &acc[t]);
+  }
+  /* reduction in row order */
+  memset(g_color, 0, sizeof(double) * 3 * (size_t)N);
+  memset(g_opac, 0, sizeof(double) * (size_t)N);
+  memset(g_rad, 0, sizeof(double) * (size_t)N);
+  double *g_p = (double *)calloc((size_t)(N > 0 ? N : 1) * 3, sizeof(double));
+  double *mag_p = NULL;
+  if (g_mag) {
+    memset(g_mag, 0, sizeof(double) * (5 * (size_t)N + 6));
+    mag_p = (double *)calloc((size_t)(N > 0 ? N : 1) * 3, sizeof(double));
+  }
+  for (int t = 0; t < nt; t++) {
+    for (size_t i = 0; i < 3 * (size_t)N; i++) { g_color[i] += acc[t].g_color[i]; g_p[i] += acc[t].g_p[i]; }
+    for (size_t i = 0; i < (size_t)N; i++) { g_opac[i] += acc[t].g_opac[i]; g_rad[i] += acc[t].g_rad[i]; }
+    if (g_mag) {
+      for (size_t i = 0; i < 5 * (size_t)N; i++) g_mag[i] += acc[t].mag[i];
+      for (size_t i = 0; i < 3 * (size_t)N; i++) mag_p[i] += acc[t].mag_p[i];
+    }
+    bwd_acc_free(&acc[t]);
+  }
+  free(acc);
   /* twist (rho, phi) of the left perturbation: dp/drho = I, dp/dphi = -[p]x */
   for (int m = 0; m < 6; m++) g_twist[m] = 0.0;
   for (int32_t g = 0; g < N; g++) {
@@ -705,7 +805,7 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
     }
   }
   free(mag_p);
-  free(a); free(G); free(T); free(qw); free(g_p);
+  free(g_p);
   lists_free(&L);
   scene_free(&s);
   return 0;

@@ -85,6 +85,8 @@ SIGNATURES = {
     "vtgs_track_step": (C.c_int, [_P, _P, _I32, _P, _P]),
     "vtgs_map_step": (C.c_int, [_P, _P, _P, _P, _P]),
     "vtgs_debug_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "vtgs_debug_images": (C.c_int, [_P, _P, _P, _P]),
+    "vtgs_debug_gather": (C.c_int, [_P, _P]),
     "vtgs_stage_name": (C.c_char_p, [_I32]),
     "vtgs_plan_timing": (C.c_int, [_P, _I32, _P, _P]),
 }

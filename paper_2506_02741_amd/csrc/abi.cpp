@@ -98,14 +98,20 @@ struct vtgs_plan {
   void *pinned = nullptr;
   size_t pinned_cap = 0;
   hipEvent_t upload_done = nullptr;
-  bool bound = false, fwd_done = false;
+  bool bound = false, fwd_done = false, slots_done = false;
   // stage timing (HIP events around every stage while enabled)
   bool timing = false;
-  // captured tracking iterations (replayed by track_step)
-  hipGraphExec_t graph = nullptr;
-  int32_t graph_iters = 0;
-  float *graph_loss = nullptr;
-  vtgs_track_cfg graph_cfg{};
+  // captured tracking iterations (replayed by track_step), one per frame
+  // length, loss array and configuration, least recently used dropped first
+  struct TrackGraph {
+    hipGraphExec_t exec = nullptr;
+    int32_t iters = 0;
+    float *loss = nullptr;
+    vtgs_track_cfg cfg{};
+    uint64_t used = 0;
+  };
+  std::vector<TrackGraph> graphs;
+  uint64_t graph_clock = 0;
   std::vector<hipEvent_t> ev_pool;
   struct EvUse { int stage; size_t start, stop; int launches; };
   std::vector<EvUse> ev_used;  // recorded stage intervals
@@ -476,10 +482,15 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
     p->ssim_gy = (maxh + 15) / 16;
     // default room: a Gaussian of extent R ~ 4-5 px covers about (1 + 10/B)^2
     // tiles of side B; keep 50% headroom
+    // the compositing kernels index tile lists with 32-bit signed positions
+    constexpr int64_t kMaxCap = (1ll << 31) - 1;
+    if (pair_capacity > kMaxCap) {
+      delete p;
+      return fail(VTGS_E_ARG, "plan_create: pair_capacity above 2^31 - 1");
+    }
     const double per = 1.5 * (1.0 + 10.0 / P.tile) * (1.0 + 10.0 / P.tile);
-    int64_t cap = pair_capacity > 0 ? pair_capacity : (int64_t)std::ceil(per * (double)n_rec) + 65536;
-    cap = std::max<int64_t>(cap, 1);
-    if (cap > 0xFFFFFFFFll) cap = 0xFFFFFFFFll;
+    const double want = pair_capacity > 0 ? (double)pair_capacity : std::ceil(per * (double)n_rec) + 65536.0;
+    const int64_t cap = std::max<int64_t>(1, (int64_t)std::min(want, (double)kMaxCap));
     p->cap = cap;
     layout(p);
     *out = p;
@@ -497,7 +508,7 @@ void vtgs_plan_destroy(vtgs_plan *p) {
   }
   if (p->pinned) pinned_give(p->pinned, p->pinned_cap);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  if (p->graph) (void)hipGraphExecDestroy(p->graph);
+  for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   delete p;
 }
 
@@ -536,10 +547,9 @@ int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
     if (!p->kf_use.empty()) std::memcpy(h + p->desc_use, p->kf_use.data(), p->kf_use.size() * sizeof(DevKFUse));
     p->ws = (char *)ws;
     make_ws(p);
-    if (p->graph) {  // captured pointers refer to the previous binding
-      (void)hipGraphExecDestroy(p->graph);
-      p->graph = nullptr;
-    }
+    // captured pointers refer to the previous binding
+    for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
     HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(p->upload_done, st));
     HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
@@ -547,6 +557,7 @@ int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
     HIP_OK(launch_fill_u32(p->w.tile_fill, 0u, p->n_tiles, st));
     p->bound = true;
     p->fwd_done = false;
+    p->slots_done = false;
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "plan_bind: unexpected exception");
@@ -596,6 +607,7 @@ int vtgs_render_bwd(vtgs_plan *p, const float *g_rgb, const float *g_depth, cons
     const Ws &w = p->w;
     if (mode & 2) STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
     STAGE(p, ST_BWD, st, launch_composite_bwd(w, g_rgb, g_depth, g_sil, mode, st));
+    if (mode & 2) p->slots_done = true;
     if (mode & 2) STAGE(p, ST_REDUCE, st, launch_gather(w, p->max_learn_n, st));
     if (mode & 1) STAGE(p, ST_REDUCE, st, launch_twist_reduce(w, g_twist, st));
     return VTGS_OK;
@@ -628,11 +640,18 @@ int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, floa
       return VTGS_OK;
     }
     const int32_t g = iters <= 64 ? iters : 1;
-    if (!p->graph || p->graph_iters != g || p->graph_loss != loss ||
-        std::memcmp(&p->graph_cfg, cfg, sizeof(vtgs_track_cfg)) != 0) {
-      if (p->graph) {
-        HIP_OK(hipGraphExecDestroy(p->graph));
-        p->graph = nullptr;
+    vtgs_plan::TrackGraph *tg = nullptr;
+    for (auto &e : p->graphs)
+      if (e.iters == g && e.loss == loss && std::memcmp(&e.cfg, cfg, sizeof(vtgs_track_cfg)) == 0)
+        tg = &e;
+    if (!tg) {
+      constexpr size_t kMaxGraphs = 4;
+      if (p->graphs.size() >= kMaxGraphs) {
+        size_t old = 0;
+        for (size_t i = 1; i < p->graphs.size(); i++)
+          if (p->graphs[i].used < p->graphs[old].used) old = i;
+        HIP_OK(hipGraphExecDestroy(p->graphs[old].exec));
+        p->graphs.erase(p->graphs.begin() + (std::ptrdiff_t)old);
       }
       HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
       int rc = VTGS_OK;
@@ -644,17 +663,18 @@ int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, floa
         return rc;
       }
       if (ec != hipSuccess) return fail(VTGS_E_HIP, std::string("stream capture: ") + hipGetErrorString(ec));
-      const hipError_t ei = hipGraphInstantiate(&p->graph, graph, nullptr, nullptr, 0);
+      vtgs_plan::TrackGraph e;
+      const hipError_t ei = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
-      if (ei != hipSuccess) {
-        p->graph = nullptr;
-        return fail(VTGS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
-      }
-      p->graph_iters = g;
-      p->graph_loss = loss;
-      p->graph_cfg = *cfg;
+      if (ei != hipSuccess) return fail(VTGS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      e.iters = g;
+      e.loss = loss;
+      e.cfg = *cfg;
+      p->graphs.push_back(e);
+      tg = &p->graphs.back();
     }
-    for (int done = 0; done + g <= iters; done += g) HIP_OK(hipGraphLaunch(p->graph, st));
+    tg->used = ++p->graph_clock;
+    for (int done = 0; done + g <= iters; done += g) HIP_OK(hipGraphLaunch(tg->exec, st));
     for (int it = (iters / g) * g; it < iters; it++)
       if (int rc = track_iteration(p, *cfg, loss, st)) return rc;
     return VTGS_OK;
@@ -684,6 +704,7 @@ int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *l
     if (p->any_learnable) {
       STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
       STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 2, st));
+      p->slots_done = true;
     }
     STAGE(p, ST_UPDATE, st,
           launch_map_update(w, *cfg, step, loss, p->any_learnable ? p->max_learn_n : 0, st));
@@ -739,6 +760,32 @@ int vtgs_debug_state(vtgs_plan *p, float *records, int32_t *rect, uint32_t *rang
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "debug_state: unexpected exception");
+  }
+}
+
+int vtgs_debug_images(vtgs_plan *p, float *img, float *gimg, void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)p->P * 5 * sizeof(float);
+    if (img) HIP_OK(hipMemcpyAsync(img, p->w.img, bytes, hipMemcpyDeviceToDevice, st));
+    if (gimg) HIP_OK(hipMemcpyAsync(gimg, p->w.gimg, bytes, hipMemcpyDeviceToDevice, st));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "debug_images: unexpected exception");
+  }
+}
+
+int vtgs_debug_gather(vtgs_plan *p, void *stream) {
+  try {
+    if (int rc = check_bound(p)) return rc;
+    if (!p->any_learnable) return fail(VTGS_E_ARG, "debug_gather: no learnable keyframe");
+    if (!p->slots_done)
+      return fail(VTGS_E_ARG, "debug_gather: no backward to colour/opacity/radius on this plan yet");
+    HIP_OK(launch_gather(p->w, p->max_learn_n, (hipStream_t)stream));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "debug_gather: unexpected exception");
   }
 }
 

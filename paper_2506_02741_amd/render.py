@@ -302,6 +302,21 @@ class Plan:
                     n_pairs=npairs)
 
 
+    def debug_images(self, stream=None):
+        """(img [5, P], gimg [5, P]): the internal RGB/depth/silhouette of the
+        last fused step and the upstream gradients map_step formed."""
+        img = torch.empty(5, self.P, device=self.device)
+        gimg = torch.empty(5, self.P, device=self.device)
+        check(self.L.vtgs_debug_images(self.h, _ptr(img), _ptr(gimg), _stream(stream)))
+        return img, gimg
+
+    def debug_gather(self, stream=None):
+        """Add the per-Gaussian gradients of the last backward to colour,
+        opacity and radius (those map_step's Adam step used) into the
+        learnable keyframes' g_color / g_opacity / g_radius."""
+        check(self.L.vtgs_debug_gather(self.h, _stream(stream)))
+
+
 def plan_checked(keyframes, views, prm=None, pair_capacity=0, device=None, run=None):
     """Create a plan, run ``run(plan)`` and, if the (Gaussian, tile) pairs
     overflowed the capacity, re-plan with room for what was needed."""
@@ -337,6 +352,11 @@ class _RenderFn(torch.autograd.Function):
         if plan.generation != ctx.gen:
             raise RuntimeError("the plan rendered again before this backward; one outstanding "
                                "forward per plan")
+        # a forward whose (Gaussian, tile) pairs overflowed the plan's capacity
+        # rendered from truncated tile lists: refuse to differentiate it
+        rc, need = plan.status(clear=False)
+        if rc != _lib.VTGS_OK:
+            raise _lib.VtgsError(rc, _lib.last_error())
         learn = [k for k in plan.keyframes if k.learnable]
         for k in learn:
             k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()

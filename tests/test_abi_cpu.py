@@ -150,3 +150,34 @@ def test_bench_traffic_summary_tracks_kernel_sources(tmp_path, monkeypatch):
     assert b.measured_traffic("composite_bwd") == 1234.0
     src.write_bytes(b"kernel source, changed")
     assert b.measured_traffic("composite_bwd") is None
+
+
+def test_pair_capacity_limit(L):
+    """Tile lists are indexed with 32-bit signed positions: an explicit
+    capacity above 2^31 - 1 is an argument error, and the default room is
+    clamped to it."""
+    from paper_2506_02741_amd import _lib
+    import ctypes as C
+    kfs, views = [_kf()], [_view()]
+    ka = (_lib.vtgs_keyframe * 1)(*kfs)
+    va = (_lib.vtgs_view * 1)(*views)
+    p = _lib.default_params()
+    h = C.c_void_p()
+    assert L.vtgs_plan_create(ka, 1, va, 1, C.byref(p), (1 << 31), C.byref(h)) == _lib.VTGS_E_ARG
+    assert "2^31" in _lib.last_error() and not h.value
+    assert L.vtgs_plan_create(ka, 1, va, 1, C.byref(p), (1 << 31) - 1, C.byref(h)) == _lib.VTGS_OK
+    try:
+        assert L.vtgs_plan_pair_capacity(h) == (1 << 31) - 1
+    finally:
+        L.vtgs_plan_destroy(h)
+
+
+def test_debug_entries_need_a_bound_plan(L):
+    from paper_2506_02741_amd import _lib
+    rc, h = _create(L, [_kf(learnable=1)], [_view()])
+    try:
+        assert L.vtgs_debug_images(h, None, None, None) == _lib.VTGS_E_WORKSPACE
+        assert L.vtgs_debug_gather(h, None) == _lib.VTGS_E_WORKSPACE
+    finally:
+        L.vtgs_plan_destroy(h)
+    assert L.vtgs_debug_gather(None, None) == _lib.VTGS_E_ARG

@@ -30,6 +30,7 @@ class _OraclePlan:
         r[:, 5] = kf.opacity
         self.prm = prm
         self.n_tiles = ranges.shape[0]
+        self.layout = [(int(view.cam[4]), int(view.cam[5]), 0, 0)]
         self._state = dict(records=torch.from_numpy(r),
                            ranges=torch.from_numpy(ranges.astype(np.int64)),
                            ids=torch.from_numpy(vals.astype(np.int64)))
@@ -85,7 +86,7 @@ def test_scan_counts_match_walk_and_oracle(orc):
     prm = orc.params()
     plan = _OraclePlan(orc, view, kf, prm)
     W, H = int(view.cam[4]), int(view.cam[5])
-    got = bench.scan_counts(plan, W, H)
+    got = bench.scan_counts(plan)
     assert got == _walk(plan, W, H)
     out = orc.render(view, [kf], prm)
     ref = int(out["n_contrib"].sum())

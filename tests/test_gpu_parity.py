@@ -503,11 +503,11 @@ def test_bench_work_counter_on_gpu_state(R, orc, tile):
     plan = R.Plan([gpu_kf(R, fr)], [R.View(cam.as_tuple(), vpose)], R.params(tile=tile))
     plan.render_fwd()
     assert plan.status()[0] == 0
-    got = bench.scan_counts(plan, cam.width, cam.height)
+    got = bench.scan_counts(plan)
     okf = oracle_kf(orc, fr)
     ov = orc.ViewSpec(cam.as_tuple(), vpose)
     prm = orc.params(tile=tile)
-    assert got == bench.scan_counts(_OraclePlan(orc, ov, okf, prm), cam.width, cam.height)
+    assert got == bench.scan_counts(_OraclePlan(orc, ov, okf, prm))
     out = orc.render(ov, [okf], prm)
     assert abs(got["contrib"] - int(out["n_contrib"].sum())) <= int(out["marginal"].sum())
 

@@ -489,3 +489,41 @@ def test_paper_constants_golden(orc):
     # the oracle's Keyframe stores exactly colour(3) + opacity + radius learnable values
     f, kf = toy(orc)
     assert kf.color.shape[0] + 1 + 1 == c["params_per_gaussian"]["value"]
+
+
+def test_relative_pose_centres_against_fp64(orc):
+    """The camera-frame centre of a view-tied Gaussian (Sec. 3.2: the pixel
+    back-projected with its keyframe's depth and pose, then seen from the
+    view) computed independently in FP64 from the world->camera poses:
+    world point X_w = R_k^T (X_k - t_k), view point R_v X_w + t_v.  The FP32
+    records agree to float rounding; the inverse composition T_k T_v^-1 (a
+    plausible slip that rigid invariance alone does not catch) is off by
+    centimetres on the same scene."""
+    rng = np.random.default_rng(21)
+    W, H = 40, 30
+    cam = (35.0, 36.0, 19.5, 15.25, W, H)
+    Tk = orc.se3_exp(np.array([0.4, -0.3, 0.2, 0.3, -0.5, 0.25])).astype(np.float32)
+    Tv = orc.se3_exp(np.array([0.35, -0.2, 0.3, 0.33, -0.42, 0.2])).astype(np.float32)
+    depth = rng.uniform(1.0, 3.0, (H, W)).astype(np.float32)
+    kf = orc.ingest(depth, None, fx=cam[0], cam=cam, pose=Tk)
+    view = orc.ViewSpec(cam, Tv)
+    rec = orc.preprocess32(view, [kf])
+    u = (kf.pix % W).astype(np.float64)
+    v = (kf.pix // W).astype(np.float64)
+    d = kf.depth.astype(np.float64)
+    Xk = np.stack([(u - cam[2]) / cam[0] * d, (v - cam[3]) / cam[1] * d, d])
+    Rk, tk = Tk[:, :3].astype(np.float64), Tk[:, 3].astype(np.float64)
+    Rv, tv = Tv[:, :3].astype(np.float64), Tv[:, 3].astype(np.float64)
+    Xw = Rk.T @ (Xk - tk[:, None])
+    Xv = Rv @ Xw + tv[:, None]
+    got = np.stack([rec["px"], rec["py"], rec["pz"]]).astype(np.float64)
+    assert np.abs(got - Xv).max() < 2e-6
+    # the inverted composition T_k T_v^-1 moves the centres by centimetres
+    Xbad = Rk @ (Rv.T @ (Xk - tv[:, None])) + tk[:, None]
+    assert np.abs(Xbad - Xv).max() > 1e-2
+    # and the projected mean is the pinhole projection of that centre
+    ok = rec["count"] > 0
+    mx = cam[0] * Xv[0] / Xv[2] + cam[2]
+    my = cam[1] * Xv[1] / Xv[2] + cam[3]
+    assert np.abs(rec["mx"][ok] - mx[ok]).max() < 1e-4
+    assert np.abs(rec["my"][ok] - my[ok]).max() < 1e-4

@@ -78,7 +78,8 @@ REC_DTYPE = np.dtype([("px", "<f4"), ("py", "<f4"), ("pz", "<f4"), ("mx", "<f4")
 
 class Values(C.Structure):
     _fields_ = [("color", C.c_void_p), ("opacity", C.c_void_p), ("radius", C.c_void_p),
-                ("twist", C.c_double * 6), ("geometry64", C.c_int32)]
+                ("twist", C.c_double * 6), ("geometry64", C.c_int32), ("depth", C.c_void_p),
+                ("kf_twist", C.c_void_p)]
 
 
 _libs = {}
@@ -125,8 +126,12 @@ def lib():
         L.orc_tile_lists.argtypes = [P, P, P, P, P, P, C.c_int64]
         L.orc_render_fwd.restype = C.c_int
         L.orc_render_fwd.argtypes = [P, P, P, P, C.c_float, C.c_int32, P, P, P, P, P, P, P]
+        L.orc_visibility.restype = C.c_int
+        L.orc_visibility.argtypes = [P, P, P, C.c_int32, P, P, P, C.c_float, C.c_float, P, P]
+        L.orc_render_alt.restype = C.c_int
+        L.orc_render_alt.argtypes = [P, P, P, P, C.c_float, C.c_int32, P, C.c_int32, P, P, P, P]
         L.orc_render_bwd.restype = C.c_int
-        L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_track_loss.restype = C.c_double
         L.orc_track_loss.argtypes = [C.c_int32, P, P, P, P, P, P, C.c_double, C.c_double,
                                      C.c_double, P, P]
@@ -208,17 +213,22 @@ def _kf_array(kfs):
     return arr
 
 
-def _values(n, color=None, opacity=None, radius=None, twist=None, geometry64=False):
+def _values(n, color=None, opacity=None, radius=None, twist=None, geometry64=False, depth=None,
+            kf_twist=None):
     keep = []
-    c = o = r = None
+    c = o = r = d = kt = None
     if color is not None:
         c = _f64(np.asarray(color).reshape(3, n)); keep.append(c)
     if opacity is not None:
         o = _f64(opacity); keep.append(o)
     if radius is not None:
         r = _f64(radius); keep.append(r)
+    if depth is not None:
+        d = _f64(depth); keep.append(d)
+    if kf_twist is not None:
+        kt = _f64(np.asarray(kf_twist).reshape(-1, 6)); keep.append(kt)
     tw = (C.c_double * 6)(*(twist if twist is not None else (0.0,) * 6))
-    return Values(_p(c), _p(o), _p(r), tw, 1 if geometry64 else 0), keep
+    return Values(_p(c), _p(o), _p(r), tw, 1 if geometry64 else 0, _p(d), _p(kt)), keep
 
 
 # ----------------------------------------------------------------------------
@@ -287,19 +297,22 @@ def slice_size(view, kfs):
 
 
 def render(view, kfs, prm=None, margin=2e-6, pixels=None, color=None, opacity=None,
-           radius=None, twist=None, geometry64=False):
+           radius=None, twist=None, geometry64=False, depth=None, kf_twist=None):
     """splat({g}, p) -> RGB [3,P], depth [P], silhouette [P]: FP64
     compositing on the FP32 contributor decisions (Sec. 3.3, Eq. 1 / Sec.
     3.4, Eq. 2 inputs).  By default the composited mean, conic and depth are
     those of the pinned FP32 records; geometry64=True recomputes them in FP64
-    (a smooth function of the inputs, for finite differences).
+    (a smooth function of the inputs, for finite differences).  ``depth``
+    [N] overrides the tied depths and ``kf_twist`` [kf_count, 6] left-twists
+    the slice's keyframe poses, both in FP64 (values only: the decisions
+    stay those of the keyframes' float data).
     ``pixels`` selects row-major pixel indices (brute force per pixel)."""
     L = lib()
     prm = prm or params()
     ka = _kf_array(kfs)
     vs = view.cstruct()
     N = slice_size(view, kfs)
-    val, keep = _values(N, color, opacity, radius, twist, geometry64)
+    val, keep = _values(N, color, opacity, radius, twist, geometry64, depth, kf_twist)
     if pixels is None:
         P, npx, idx = view.P, -1, None
     else:
@@ -312,33 +325,96 @@ def render(view, kfs, prm=None, margin=2e-6, pixels=None, color=None, opacity=No
     if rc < 0:
         raise MemoryError("oracle render failed")
     return dict(rgb=rgb, depth=dep, sil=sil, t_final=tf, n_contrib=nc, marginal=mg.astype(bool),
-                superset_violations=int(rc))
+                marginal_kind=mg, superset_violations=int(rc))
 
 
-def render_bwd(view, kfs, g_rgb, g_depth=None, g_sil=None, prm=None, color=None,
-               opacity=None, radius=None, twist=None, geometry64=False):
-    """Exact derivative of ``render`` (contributor sets fixed) w.r.t. colour,
-    opacity, radius of every Gaussian of the slice and the view twist."""
+def render_alternatives(view, kfs, pixels, prm=None, margin=2e-6, max_alt=4, color=None,
+                        opacity=None, radius=None, twist=None):
+    """The other outcomes of the near-tie decisions of the listed pixels
+    (Sec. 3.3 splat; the tie reading of the stop and cut-off rules): for
+    pixel i, variant j takes its j-th near-tie decision (candidate tests in
+    slice order, then stop decisions front to back) the other way.  Returns
+    n_dec [n], rgb [n, max_alt, 3], depth and sil [n, max_alt] (variants
+    j >= n_dec[i] are NaN)."""
     L = lib()
     prm = prm or params()
     ka = _kf_array(kfs)
     vs = view.cstruct()
     N = slice_size(view, kfs)
-    val, keep = _values(N, color, opacity, radius, twist, geometry64)
+    val, keep = _values(N, color, opacity, radius, twist, False)
+    idx = np.ascontiguousarray(pixels, dtype=np.int32)
+    n = int(idx.shape[0])
+    rgb = np.full((max(n, 1), max_alt, 3), np.nan); dep = np.full((max(n, 1), max_alt), np.nan)
+    sil = np.full((max(n, 1), max_alt), np.nan); nd = np.zeros(max(n, 1), np.int32)
+    rc = L.orc_render_alt(C.byref(vs), ka, C.byref(prm), C.byref(val), float(margin), n, _p(idx),
+                          int(max_alt), _p(rgb), _p(dep), _p(sil), _p(nd))
+    if rc < 0:
+        raise MemoryError("oracle alternatives failed")
+    return dict(n_dec=nd[:n], rgb=rgb[:n], depth=dep[:n], sil=sil[:n])
+
+
+def render_bwd(view, kfs, g_rgb, g_depth=None, g_sil=None, prm=None, color=None,
+               opacity=None, radius=None, twist=None, geometry64=False, depth=None,
+               kf_twist=None):
+    """Exact derivative of ``render`` (contributor sets fixed) w.r.t. colour,
+    opacity, radius of every Gaussian of the slice and the view twist, plus
+    (Sec. 3.5 bundle adjustment; the supplementary's Gaussians movable along
+    the ray) each Gaussian's tied depth and each slice keyframe's pose twist."""
+    L = lib()
+    prm = prm or params()
+    ka = _kf_array(kfs)
+    vs = view.cstruct()
+    N = slice_size(view, kfs)
+    val, keep = _values(N, color, opacity, radius, twist, geometry64, depth, kf_twist)
     P = view.P
     gr = _f64(np.asarray(g_rgb).reshape(3, P))
     gd = None if g_depth is None else _f64(g_depth)
     gs = None if g_sil is None else _f64(g_sil)
     gc = np.zeros((3, max(N, 1))); go = np.zeros(max(N, 1)); grd = np.zeros(max(N, 1))
     tw = np.zeros(6)
+    gkd = np.zeros(max(N, 1)); gkp = np.zeros((max(view.kf_count, 1), 6))
+    gkm = np.zeros(N + 6 * max(view.kf_count, 1))
     mag = np.zeros(5 * N + 6)
     rc = L.orc_render_bwd(C.byref(vs), ka, C.byref(prm), C.byref(val), _p(gr), _p(gd), _p(gs),
-                          _p(gc), _p(go), _p(grd), _p(tw), _p(mag))
+                          _p(gc), _p(go), _p(grd), _p(tw), _p(mag), _p(gkd),
+                          _p(gkp), _p(gkm))
     if rc < 0:
         raise MemoryError("oracle backward failed")
     mags = dict(color=mag[:3 * N].reshape(3, N), opacity=mag[3 * N:4 * N],
-                radius=mag[4 * N:5 * N], twist=mag[5 * N:5 * N + 6])
-    return dict(color=gc[:, :N], opacity=go[:N], radius=grd[:N], twist=tw, mag=mags)
+                radius=mag[4 * N:5 * N], twist=mag[5 * N:5 * N + 6], depth=gkm[:N],
+                kf_pose=gkm[N:N + 6 * view.kf_count].reshape(view.kf_count, 6))
+    return dict(color=gc[:, :N], opacity=go[:N], radius=grd[:N], twist=tw, mag=mags,
+                depth=gkd[:N], kf_pose=gkp[:view.kf_count])
+
+
+def visibility(src_depth, src_cam, src_pose, targets, rel_tol=0.01, z_near=0.01):
+    """Sec. 3.3 visibility check of a source frame's depth points in target
+    views: targets = [(depth [H, W], cam tuple, pose [3, 4])].  Returns
+    vis [n_tgt, H*W] bool and counts [n_tgt]."""
+    L = lib()
+    sd = _f32(np.ravel(src_depth))
+    sc = Cam(*src_cam)
+    sp = _f32(np.ravel(src_pose))
+    n = len(targets)
+    depths = [_f32(np.ravel(t[0])) for t in targets]
+    poses = [_f32(np.ravel(t[2])) for t in targets]
+    dptr = (C.c_void_p * max(n, 1))(*[d.ctypes.data for d in depths])
+    pptr = (C.c_void_p * max(n, 1))(*[q.ctypes.data for q in poses])
+    cams = (Cam * max(n, 1))(*[Cam(*t[1]) for t in targets])
+    P = sd.size
+    vis = np.zeros((max(n, 1), P), np.uint8)
+    counts = np.zeros(max(n, 1), np.int64)
+    L.orc_visibility(_p(sd), C.byref(sc), _p(sp), n, dptr, cams, pptr, float(rel_tol),
+                     float(z_near), _p(vis), _p(counts))
+    return vis[:n].astype(bool), counts[:n]
+
+
+def select_overlap(counts, n_valid, candidate_sections, gamma, n_front=3):
+    """Sec. 3.3 overlap selection, first stage: the candidate views whose
+    visible-point fraction exceeds gamma, then the n_front most front
+    (earliest) sections holding at least one of them."""
+    keep = [s for c, s in zip(counts, candidate_sections) if c > gamma * n_valid]
+    return sorted(set(keep))[:n_front]
 
 
 def track_loss(rgb, depth, sil, obs_rgb, obs_depth, vis=None, alpha=0.5, beta=1.0,
@@ -415,5 +491,6 @@ def track_iteration(view, kfs, obs_rgb, obs_depth, state, alpha=0.5, beta=1.0, l
 
 
 __all__ = ["DEFAULTS", "threads", "Keyframe", "ViewSpec", "params", "ingest", "relpose32", "preprocess32",
-           "tile_lists", "slice_size", "render", "render_bwd", "track_loss", "ssim", "map_loss",
-           "se3_exp", "adam", "compose", "track_iteration", "REC_DTYPE"]
+           "tile_lists", "slice_size", "render", "render_alternatives", "render_bwd", "track_loss", "ssim", "map_loss",
+           "se3_exp", "adam", "compose", "track_iteration", "REC_DTYPE", "visibility",
+           "select_overlap"]

@@ -206,6 +206,67 @@ int64_t orc_tile_lists(const orc_view *v, const orc_kf *kfs, const orc_params *p
 }
 
 /* ------------------------------------------------------------------------ */
+/* visibility of a frame's depth points in other views (Sec. 3.3)            */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear interpolation of a depth map at (x, y): the four neighbours
+ * must lie inside the map and hold valid (> 0) depths.  Returns 0 when the
+ * interpolation is undefined. */
+static int depth_bilinear(const float *D, int32_t W, int32_t H, float x, float y, float *out) {
+  /* decide on the float coordinates before any conversion to int */
+  if (!(x >= 0.0f && y >= 0.0f && x < (float)(W - 1) && y < (float)(H - 1))) return 0;
+  float fx0 = floorf(x), fy0 = floorf(y);
+  int32_t x0 = (int32_t)fx0, y0 = (int32_t)fy0;
+  float d00 = D[(int64_t)y0 * W + x0], d01 = D[(int64_t)y0 * W + x0 + 1];
+  float d10 = D[(int64_t)(y0 + 1) * W + x0], d11 = D[(int64_t)(y0 + 1) * W + x0 + 1];
+  if (!(d00 > 0.0f && d01 > 0.0f && d10 > 0.0f && d11 > 0.0f)) return 0;
+  float ax = x - fx0, ay = y - fy0;
+  float top = d00 + ax * (d01 - d00);
+  float bot = d10 + ax * (d11 - d10);
+  *out = top + ay * (bot - top);
+  return 1;
+}
+
+int orc_visibility(const float *src_depth, const orc_cam *src_cam, const float *src_pose,
+                   int32_t n_tgt, const float *const *tgt_depth, const orc_cam *tgt_cam,
+                   const float *const *tgt_pose, float rel_tol, float z_near, uint8_t *vis,
+                   int64_t *counts) {
+  int32_t W = src_cam->width, H = src_cam->height;
+  int64_t P = (int64_t)W * H;
+  for (int32_t t = 0; t < n_tgt; t++) {
+    float M[12];
+    orc_relpose32(tgt_pose[t], src_pose, M);
+    const orc_cam *tc = &tgt_cam[t];
+    int64_t cnt = 0;
+    for (int64_t p = 0; p < P; p++) {
+      uint8_t v = 0;
+      float d = src_depth[p];
+      if (d > 0.0f) {
+        int32_t u = (int32_t)(p % W), w = (int32_t)(p / W);
+        /* back-projection and transform in the pinned order of the records */
+        float xk = (((float)u - src_cam->cx) / src_cam->fx) * d;
+        float yk = (((float)w - src_cam->cy) / src_cam->fy) * d;
+        float zk = d;
+        float px = ((M[0] * xk + M[1] * yk) + M[2] * zk) + M[3];
+        float py = ((M[4] * xk + M[5] * yk) + M[6] * zk) + M[7];
+        float pz = ((M[8] * xk + M[9] * yk) + M[10] * zk) + M[11];
+        if (pz > z_near) {
+          float mx = tc->fx * (px / pz) + tc->cx;
+          float my = tc->fy * (py / pz) + tc->cy;
+          float Dt;
+          if (depth_bilinear(tgt_depth[t], tc->width, tc->height, mx, my, &Dt))
+            v = fabsf(pz - Dt) <= rel_tol * Dt;
+        }
+      }
+      vis[(int64_t)t * P + p] = v;
+      cnt += v;
+    }
+    if (counts) counts[t] = cnt;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* FP64 geometry of one Gaussian in one view (values and gradients)         */
 /* ------------------------------------------------------------------------ */
 
@@ -248,6 +309,25 @@ static void view_pose64(const orc_view *v, const orc_values *val, double *Tv) {
   } else {
     memcpy(Tv, T0, sizeof(T0));
   }
+}
+
+/* M = T_v T_k^-1 of slice keyframe sidx in FP64, with the view's and the
+ * keyframe's twists of `val` applied (left: pose <- exp(twist^) pose). */
+static void slice_M(const orc_view *v, const orc_kf *kfs, const orc_values *val, int32_t sidx,
+                    double *M) {
+  const orc_kf *k = &kfs[v->kf_first + sidx];
+  double Tv[12], T0[12], Tk[12], Tki[12];
+  view_pose64(v, val, Tv);
+  for (int i = 0; i < 12; i++) T0[i] = k->pose[i];
+  if (val && val->kf_twist) {
+    double E[12];
+    orc_se3_exp(val->kf_twist + 6 * sidx, E);
+    mat34_mul(E, T0, Tk);
+  } else {
+    memcpy(Tk, T0, sizeof(T0));
+  }
+  rigid_inv(Tk, Tki);
+  mat34_mul(Tv, Tki, M);
 }
 
 static void geo_of(const double *M, const orc_cam *kc, const orc_cam *vc, uint32_t pix, double d,
@@ -332,18 +412,15 @@ static int scene_build(const orc_view *v, const orc_kf *kfs, const orc_params *p
   s->opa = (double *)malloc(sizeof(double) * n1);
   if (!s->rec || !s->geo || !s->col || !s->opa) { scene_free(s); return -1; }
   orc_preprocess32(v, kfs, prm, s->rec);
-  double Tv[12];
-  view_pose64(v, val, Tv);
   int32_t id = 0;
   for (int32_t sidx = 0; sidx < v->kf_count; sidx++) {
     const orc_kf *k = &kfs[v->kf_first + sidx];
-    double Tk[12], Tki[12], M[12];
-    for (int i = 0; i < 12; i++) Tk[i] = k->pose[i];
-    rigid_inv(Tk, Tki);
-    mat34_mul(Tv, Tki, M);
+    double M[12];
+    slice_M(v, kfs, val, sidx, M);
     for (int32_t i = 0; i < k->n; i++, id++) {
       double r = (val && val->radius) ? val->radius[id] : k->radius[i];
-      geo_of(M, &k->cam, &v->cam, k->pix[i], k->depth[i], r, prm->lowpass, &s->geo[id]);
+      double d = (val && val->depth) ? val->depth[id] : k->depth[i];
+      geo_of(M, &k->cam, &v->cam, k->pix[i], d, r, prm->lowpass, &s->geo[id]);
       if (!(val && val->geometry64) && s->rec[id].count > 0) {
         /* composite the pinned FP32 record: mean, conic, depth */
         const orc_rec *rc = &s->rec[id];
@@ -386,25 +463,38 @@ static int near_rel(float x, float thr, float margin) {
   return fabsf(x - thr) <= margin * fabsf(thr);
 }
 
+/* Kinds of near-tie a test reports in its flag byte. */
+enum { MARG_CAND = 1, MARG_CLAMP = 2, MARG_STOP = 4 };
+
 /* FP32 per-(pixel, Gaussian) test: q <= Q_CUT and alpha >= alpha_min.
- * Returns 1 if the Gaussian is a candidate.  Sets *marg on near-ties. */
+ * Returns 1 if the Gaussian is a candidate.  ORs MARG_CAND into *marg when
+ * the candidate decision is a near-tie: q within `margin` (relative) of
+ * Q_CUT while the alpha test passes or ties, or alpha within `margin` of
+ * alpha_min while the q test passes or ties; with flip != 0 the tied tests
+ * are taken the other way.  ORs MARG_CLAMP when the alpha_max clamp ties
+ * (which moves alpha by at most `margin`, not the candidate set). */
 static int test32(const orc_rec *r, float o, int32_t u, int32_t v, const orc_params *prm,
-                  float margin, uint8_t *clamped, uint8_t *marg) {
+                  float margin, int flip, uint8_t *clamped, uint8_t *marg) {
   float dx = (float)u - r->mx, dy = (float)v - r->my;
   /* pinned order: q = fma(qc*dy, dy, fma(2qb*dx, dy, (qa*dx)*dx)) */
   float q = (r->qa * dx) * dx;
   q = fmaf((2.0f * r->qb) * dx, dy, q);
   q = fmaf(r->qc * dy, dy, q);
-  if (near_rel(q, prm->q_cut, margin)) *marg = 1;
-  if (!(q <= prm->q_cut)) return 0;
-  float G = expf(-0.5f * q);
-  float a = o * G;
+  float a = o * expf(-0.5f * q);
   /* G <= 1, so the clamp can only engage (and tie) when o > alpha_max */
-  if (o > prm->alpha_max && near_rel(a, prm->alpha_max, margin)) *marg = 1;
+  if (o > prm->alpha_max && near_rel(a, prm->alpha_max, margin)) *marg |= MARG_CLAMP;
   *clamped = a > prm->alpha_max;
   if (*clamped) a = prm->alpha_max;
-  if (near_rel(a, prm->alpha_min, margin)) *marg = 1;
-  return a >= prm->alpha_min;
+  int pq = q <= prm->q_cut, pa = a >= prm->alpha_min;
+  int tq = near_rel(q, prm->q_cut, margin), ta = near_rel(a, prm->alpha_min, margin);
+  if ((tq && (pa || ta)) || (ta && (pq || tq))) {
+    *marg |= MARG_CAND;
+    if (flip) {
+      if (tq) pq = !pq;
+      if (ta) pa = !pa;
+    }
+  }
+  return pq && pa;
 }
 
 static float alpha32(const orc_rec *r, float o, int32_t u, int32_t v, const orc_params *prm) {
@@ -464,10 +554,10 @@ static int lists_build(const orc_view *v, const orc_kf *kfs, const orc_params *p
       for (int32_t y = y0; y <= y1; y++)
         for (int32_t x = x0; x <= x1; x++) {
           uint8_t cl = 0, mg = 0;
-          int ok = test32(r, o, x, y, prm, margin, &cl, &mg);
+          int ok = test32(r, o, x, y, prm, margin, 0, &cl, &mg);
           int64_t p = (int64_t)y * W + x;
           if (pass == 0) {
-            if (mg) L->marg[p] = 1;
+            L->marg[p] |= mg;
             if (ok) {
 #ifdef _OPENMP
 #pragma omp atomic
@@ -508,7 +598,7 @@ static int64_t pixel_list(const orc_view *v, const orc_kf *kfs, const orc_params
     const orc_rec *r = &s->rec[g];
     if (!r->count) continue;
     uint8_t cl = 0;
-    if (test32(r, opa32(v, kfs, g), x, y, prm, margin, &cl, marg)) {
+    if (test32(r, opa32(v, kfs, g), x, y, prm, margin, 0, &cl, marg)) {
       out[n].zb = fbits(r->pz);
       out[n].id = g;
       out[n].clamped = cl;
@@ -521,10 +611,13 @@ static int64_t pixel_list(const orc_view *v, const orc_kf *kfs, const orc_params
 
 /* Front-to-back compositing of one pixel.  FP32 transmittance decides when
  * to stop; colour, depth and transmittance values are accumulated in FP64.
- * Returns the number of contributors. */
+ * Returns the number of contributors.  With nd != NULL the near-tie stop
+ * decisions are numbered from *nd on (which is advanced) and the one
+ * numbered `flip` is taken the other way (flip < 0: none). */
 static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                          const scene_t *s, float margin, int32_t x, int32_t y, const ent *e,
-                         int64_t n, double *C, double *D, double *T_out, uint8_t *marg) {
+                         int64_t n, double *C, double *D, double *T_out, uint8_t *marg,
+                         int32_t flip, int32_t *nd) {
   float T32 = 1.0f;
   double T = 1.0;
   /* Relative uncertainty of T32 against an evaluation whose exp differs by
@@ -541,8 +634,15 @@ static int32_t composite(const orc_view *v, const orc_kf *kfs, const orc_params 
     float a32 = alpha32(r, opa32(v, kfs, g), x, y, prm);
     float Tn = T32 * (1.0f - a32);
     double un = u + (double)margin * a32 / (1.0 - a32) + (margin > 0.f ? 1.2e-7 : 0.0);
-    if (fabs((double)Tn - prm->t_min) <= un * prm->t_min) *marg = 1;
-    if (Tn < prm->t_min) break;
+    int stop = Tn < prm->t_min;
+    if (fabs((double)Tn - prm->t_min) <= un * prm->t_min) {
+      *marg |= MARG_STOP;
+      if (nd) {
+        if (*nd == flip) stop = !stop;
+        (*nd)++;
+      }
+    }
+    if (stop) break;
     double w[2];
     double q = q_at(&s->geo[g], x, y, w);
     double a = e[i].clamped ? (double)prm->alpha_max : s->opa[g] * exp(-0.5 * q);
@@ -578,7 +678,7 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
       double C[3], D, T;
       uint8_t mg = L.marg[p];
       int32_t k = composite(v, kfs, prm, &s, margin, (int32_t)(p % W), (int32_t)(p / W),
-                            L.e + L.off[p], L.off[p + 1] - L.off[p], C, &D, &T, &mg);
+                            L.e + L.off[p], L.off[p + 1] - L.off[p], C, &D, &T, &mg, -1, NULL);
       for (int c = 0; c < 3; c++) rgb[c * P + p] = C[c];
       depth[p] = D;
       sil[p] = 1.0 - T;
@@ -595,7 +695,7 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
       uint8_t mg = 0;
       int64_t n = pixel_list(v, kfs, prm, &s, margin, x, y, buf, &mg);
       double C[3], D, T;
-      int32_t k = composite(v, kfs, prm, &s, margin, x, y, buf, n, C, &D, &T, &mg);
+      int32_t k = composite(v, kfs, prm, &s, margin, x, y, buf, n, C, &D, &T, &mg, -1, NULL);
       for (int c = 0; c < 3; c++) rgb[c * P + i] = C[c];
       depth[i] = D;
       sil[i] = 1.0 - T;
@@ -607,6 +707,103 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
   }
   scene_free(&s);
   return rc;
+}
+
+/* The other outcomes of a pixel's near-tie decisions.  A decision within
+ * `margin` of its threshold (a candidate test, or a stop) may legitimately
+ * go either way in an evaluation whose exp differs by that much; the pixel's
+ * near-tie decisions are numbered as they are met -- candidate tests in
+ * slice order, then stop decisions front to back -- and variant j is the
+ * pixel with decision j taken the other way and every later decision taken
+ * by the FP32 tests.  Only the Gaussians whose scan box (mu +- (R + 2))
+ * holds the pixel are tested: beyond it q exceeds Q_CUT by a wide margin. */
+int orc_render_alt(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
+                   const orc_values *val, float margin, int32_t n_px, const int32_t *px_idx,
+                   int32_t max_alt, double *rgb, double *depth, double *sil, int32_t *n_dec) {
+  scene_t s;
+  if (scene_build(v, kfs, prm, val, &s)) return -1;
+  int32_t W = v->cam.width, H = v->cam.height;
+  int64_t P = (int64_t)W * H;
+  /* request index of every pixel (-1: not requested) */
+  int32_t *req = (int32_t *)malloc(sizeof(int32_t) * (size_t)(P > 0 ? P : 1));
+  int64_t *off = (int64_t *)calloc((size_t)n_px + 1, sizeof(int64_t));
+  if (!req || !off) { free(req); free(off); scene_free(&s); return -1; }
+  for (int64_t p = 0; p < P; p++) req[p] = -1;
+  for (int32_t i = 0; i < n_px; i++) req[px_idx[i]] = i;
+  int32_t *near = NULL;
+  int64_t *fill = NULL;
+  /* two passes over the Gaussians in slice order: count, then fill, so each
+   * pixel's Gaussians are listed in ascending local id */
+  for (int pass = 0; pass < 2; pass++) {
+    if (pass == 1) {
+      for (int32_t i = 0; i < n_px; i++) off[i + 1] += off[i];
+      near = (int32_t *)malloc(sizeof(int32_t) * (size_t)(off[n_px] > 0 ? off[n_px] : 1));
+      fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_px > 0 ? n_px : 1));
+      if (!near || !fill) { free(near); free(fill); free(req); free(off); scene_free(&s); return -1; }
+      for (int32_t i = 0; i < n_px; i++) fill[i] = off[i];
+    }
+    for (int32_t g = 0; g < s.N; g++) {
+      const orc_rec *r = &s.rec[g];
+      if (!r->count) continue;
+      int32_t x0 = (int32_t)floorf(r->mx - r->ext) - 2, x1 = (int32_t)ceilf(r->mx + r->ext) + 2;
+      int32_t y0 = (int32_t)floorf(r->my - r->ext) - 2, y1 = (int32_t)ceilf(r->my + r->ext) + 2;
+      if (x0 < 0) x0 = 0;
+      if (y0 < 0) y0 = 0;
+      if (x1 > W - 1) x1 = W - 1;
+      if (y1 > H - 1) y1 = H - 1;
+      for (int32_t y = y0; y <= y1; y++)
+        for (int32_t x = x0; x <= x1; x++) {
+          int32_t i = req[(int64_t)y * W + x];
+          if (i < 0) continue;
+          if (pass == 0) off[i + 1]++;
+          else near[fill[i]++] = g;
+        }
+    }
+  }
+  free(fill);
+  ent *buf = (ent *)malloc(sizeof(ent) * (size_t)(s.N > 0 ? s.N : 1));
+  if (!buf) { free(near); free(req); free(off); scene_free(&s); return -1; }
+  for (int32_t i = 0; i < n_px; i++) {
+    int32_t x = px_idx[i] % W, y = px_idx[i] / W;
+    int32_t total = 0;
+    for (int32_t flip = -1; flip < (total < max_alt ? total : max_alt); flip++) {
+      int32_t nd = 0;
+      int64_t n = 0;
+      for (int64_t j = off[i]; j < off[i + 1]; j++) {
+        int32_t g = near[j];
+        const orc_rec *r = &s.rec[g];
+        uint8_t cl = 0, mg = 0;
+        float o = opa32(v, kfs, g);
+        int ok = test32(r, o, x, y, prm, margin, 0, &cl, &mg);
+        if (mg & MARG_CAND) {
+          if (nd == flip) ok = test32(r, o, x, y, prm, margin, 1, &cl, &mg);
+          nd++;
+        }
+        if (ok) {
+          buf[n].zb = fbits(r->pz);
+          buf[n].id = g;
+          buf[n].clamped = cl;
+          n++;
+        }
+      }
+      qsort(buf, (size_t)n, sizeof(ent), cmp_ent);
+      double C[3], D, T;
+      uint8_t mg = 0;
+      composite(v, kfs, prm, &s, margin, x, y, buf, n, C, &D, &T, &mg, flip, &nd);
+      if (flip < 0) {
+        total = nd;
+        n_dec[i] = nd;
+        continue;
+      }
+      size_t o = (size_t)i * (size_t)max_alt + (size_t)flip;
+      for (int c = 0; c < 3; c++) rgb[3 * o + c] = C[c];
+      depth[o] = D;
+      sil[o] = 1.0 - T;
+    }
+  }
+  free(buf); free(near); free(req); free(off);
+  scene_free(&s);
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -731,7 +928,8 @@ static void bwd_pixels(const orc_view *v, const orc_kf *kfs, const orc_params *p
 int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                    const orc_values *val, const double *g_rgb, const double *g_depth,
                    const double *g_sil, double *g_color, double *g_opac, double *g_rad,
-                   double *g_twist, double *g_mag) {
+                   double *g_twist, double *g_mag, double *g_kdepth, double *g_kpose,
+                   double *g_kmag) {
   scene_t s;
   if (scene_build(v, kfs, prm, val, &s)) return -1;
   lists_t L;
@@ -802,6 +1000,52 @@ int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
       mt[3] += fabs(pp[1]) * mp[2] + fabs(pp[2]) * mp[1];
       mt[4] += fabs(pp[2]) * mp[0] + fabs(pp[0]) * mp[2];
       mt[5] += fabs(pp[0]) * mp[1] + fabs(pp[1]) * mp[0];
+    }
+  }
+  /* the keyframe side of the centres: X = d n in the keyframe camera, n the
+   * pixel's ray (z = 1), p = R X + t with (R, t) = T_v T_k^-1.  With
+   * h = R^T dL/dp:  dL/dd = h . n;  a left twist of T_k moves X to
+   * exp(-twist^) X, so dL/drho_k = -sum h and dL/dphi_k = -sum X x h. */
+  if (g_kdepth || g_kpose) {
+    int32_t id = 0;
+    for (int32_t sidx = 0; sidx < v->kf_count; sidx++) {
+      const orc_kf *k = &kfs[v->kf_first + sidx];
+      double M[12], G6[6] = {0, 0, 0, 0, 0, 0}, A6[6] = {0, 0, 0, 0, 0, 0};
+      slice_M(v, kfs, val, sidx, M);
+      for (int32_t i = 0; i < k->n; i++, id++) {
+        const double *gp = &g_p[3 * id];
+        double h[3], ha[3];
+        for (int c = 0; c < 3; c++) h[c] = M[c] * gp[0] + M[4 + c] * gp[1] + M[8 + c] * gp[2];
+        int32_t u = (int32_t)(k->pix[i] % (uint32_t)k->cam.width);
+        int32_t w = (int32_t)(k->pix[i] / (uint32_t)k->cam.width);
+        double n[3] = {(u - (double)k->cam.cx) / k->cam.fx, (w - (double)k->cam.cy) / k->cam.fy, 1.0};
+        double d = (val && val->depth) ? val->depth[id] : k->depth[i];
+        if (g_kdepth) g_kdepth[id] = h[0] * n[0] + h[1] * n[1] + h[2] * n[2];
+        double X[3] = {d * n[0], d * n[1], d * n[2]};
+        G6[0] -= h[0];
+        G6[1] -= h[1];
+        G6[2] -= h[2];
+        G6[3] -= X[1] * h[2] - X[2] * h[1];
+        G6[4] -= X[2] * h[0] - X[0] * h[2];
+        G6[5] -= X[0] * h[1] - X[1] * h[0];
+        if (g_kmag && mag_p) {
+          /* the same with every summand in absolute value */
+          const double *mp = &mag_p[3 * id];
+          for (int c = 0; c < 3; c++)
+            ha[c] = fabs(M[c]) * mp[0] + fabs(M[4 + c]) * mp[1] + fabs(M[8 + c]) * mp[2];
+          g_kmag[id] = ha[0] * fabs(n[0]) + ha[1] * fabs(n[1]) + ha[2];
+          A6[0] += ha[0];
+          A6[1] += ha[1];
+          A6[2] += ha[2];
+          A6[3] += fabs(X[1]) * ha[2] + fabs(X[2]) * ha[1];
+          A6[4] += fabs(X[2]) * ha[0] + fabs(X[0]) * ha[2];
+          A6[5] += fabs(X[0]) * ha[1] + fabs(X[1]) * ha[0];
+        }
+      }
+      if (g_kpose)
+        for (int c = 0; c < 6; c++) g_kpose[6 * sidx + c] = G6[c];
+      if (g_kmag && mag_p)
+        for (int c = 0; c < 6; c++) g_kmag[(size_t)N + 6 * sidx + c] = A6[c];
     }
   }
   free(mag_p);

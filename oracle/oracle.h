@@ -71,7 +71,8 @@ typedef struct {
 } orc_rec;
 
 /* Optional FP64 value inputs over the slice's local ids (NULL => the
- * keyframes' float values), plus a left twist applied to the view pose.
+ * keyframes' float values), plus a left twist applied to the view pose and
+ * (kf_twist) to each keyframe pose of the slice.
  * geometry64 = 0: the forward composites, in FP64, the projected mean,
  * conic and depth of the pinned FP32 records (the definition both sides
  * share bit for bit); derivatives use the FP64 geometry.  geometry64 = 1:
@@ -84,6 +85,8 @@ typedef struct {
   const double *radius;    /* [N]    */
   double twist[6];         /* (rho, phi): pose <- exp(twist^) * pose */
   int32_t geometry64;
+  const double *depth;     /* [N] tied depth (the Gaussian's place on its ray) */
+  const double *kf_twist;  /* [kf_count][6]: keyframe pose <- exp(twist^) * pose */
 } orc_values;
 
 /* ---- keyframe ingestion: valid pixels -> compact Gaussian list ---- */
@@ -102,16 +105,42 @@ int32_t orc_preprocess32(const orc_view *v, const orc_kf *kfs, const orc_params 
 int64_t orc_tile_lists(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                        uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t cap);
 
+/* ---- visibility (Sec. 3.3): a source frame's depth point -- pixel (u, v)
+ * with depth d > 0, back-projected with the source intrinsics and moved
+ * from the source pose to a target pose -- is visible in the target when
+ * its target-camera depth p_z > z_near lies within rel_tol (1 %) of the
+ * target depth map bilinearly interpolated at its projection (all four
+ * neighbours inside the map and valid).  FP32 in a pinned order (no FMA):
+ * the relative pose, back-projection, transform and projection of the
+ * records, then bilinear top/bottom rows and their blend, then
+ * |p_z - D| <= rel_tol * D.  vis [n_tgt][H*W] (0/1), counts [n_tgt] the
+ * visible points per target (or NULL). ---- */
+int orc_visibility(const float *src_depth, const orc_cam *src_cam, const float *src_pose,
+                   int32_t n_tgt, const float *const *tgt_depth, const orc_cam *tgt_cam,
+                   const float *const *tgt_pose, float rel_tol, float z_near, uint8_t *vis,
+                   int64_t *counts);
+
 /* ---- forward ---- */
 /* Full image when n_px < 0 (outputs have P = W*H entries); otherwise only
  * the listed pixel indices (outputs have n_px entries).  rgb is planar
- * [3][P].  marginal[p] = 1 where some FP32 decision at that pixel lies
- * within a relative distance `margin` of its threshold.  Returns 0 on
- * success. */
+ * [3][P].  marginal[p] != 0 where some FP32 decision at that pixel lies
+ * within a relative distance `margin` of its threshold (bit 1: a candidate
+ * test, 2: the alpha_max clamp, 4: a stop decision).  Returns 0 on success
+ * (1 when the superset property failed somewhere). */
 int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                    const orc_values *val, float margin, int32_t n_px, const int32_t *px_idx,
                    double *rgb, double *depth, double *sil, double *t_final,
                    int32_t *n_contrib, uint8_t *marginal);
+
+/* The other outcomes of the listed pixels' near-tie decisions (candidate
+ * tests, then stop decisions, numbered as met): variant j of pixel i takes
+ * decision j the other way.  n_dec[i] receives the number of near-tie
+ * decisions of pixel i; rgb [n_px][max_alt][3], depth and sil
+ * [n_px][max_alt] receive variants j < min(n_dec[i], max_alt).  Returns 0
+ * on success. */
+int orc_render_alt(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
+                   const orc_values *val, float margin, int32_t n_px, const int32_t *px_idx,
+                   int32_t max_alt, double *rgb, double *depth, double *sil, int32_t *n_dec);
 
 /* ---- backward: exact derivative of the forward with the FP32 contributor
  * sets held fixed.  g_color [3][N], g_opac [N], g_rad [N] over the slice's
@@ -119,11 +148,17 @@ int orc_render_fwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
  * [5N + 6]: colour, opacity, radius, twist) receives each gradient's sum of
  * absolute summands -- every per-pixel term, and every product and sum
  * inside it, taken in absolute value -- the scale of the rounding error of
- * any evaluation of those sums in a shorter precision. ---- */
+ * any evaluation of those sums in a shorter precision.  g_kdepth (NULL or
+ * [N]) receives dLoss/d(tied depth) of every Gaussian -- its centre moved
+ * along its pixel's ray -- and g_kpose (NULL or [kf_count][6]) the gradient
+ * of a left twist (rho, phi) of each keyframe pose of the slice, through the
+ * centres of its tied Gaussians; g_kmag (NULL, or [N + 6 kf_count] when
+ * g_mag is given) their sums of absolute summands. ---- */
 int orc_render_bwd(const orc_view *v, const orc_kf *kfs, const orc_params *prm,
                    const orc_values *val, const double *g_rgb, const double *g_depth,
                    const double *g_sil, double *g_color, double *g_opac, double *g_rad,
-                   double *g_twist, double *g_mag);
+                   double *g_twist, double *g_mag, double *g_kdepth, double *g_kpose,
+                   double *g_kmag);
 
 /* ---- losses ---- */
 double orc_track_loss(int32_t P, const double *rgb, const double *depth, const double *sil,

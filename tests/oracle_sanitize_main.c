@@ -62,12 +62,17 @@ int main(int argc, char **argv) {
   int32_t pn[3];
   uint8_t pm[3];
   if (orc_render_fwd(&view, &kf, &prm, NULL, 2e-6f, 3, some, prgb, pd, ps, pt, pn, pm) < 0) return 7;
+  /* near-tie alternatives of three pixels under a wide margin */
+  double argb[3 * 3 * 4], adep[3 * 4], asil[3 * 4];
+  int32_t andec[3];
+  if (orc_render_alt(&view, &kf, &prm, NULL, 1e-2f, 3, some, 4, argb, adep, asil, andec) < 0) return 10;
   double *g_rgb = malloc(sizeof(double) * 3 * (size_t)P), *g_d = malloc(sizeof(double) * (size_t)P);
   double L1 = orc_track_loss((int32_t)P, img, dimg, sil, rgb, depth, NULL, 0.5, 1.0, 0.5, g_rgb, g_d);
   double *gc = malloc(sizeof(double) * 3 * (size_t)n), *go = malloc(sizeof(double) * (size_t)n);
   double *gr = malloc(sizeof(double) * (size_t)n), *mag = malloc(sizeof(double) * (5 * (size_t)n + 6));
   double tw[6];
-  if (orc_render_bwd(&view, &kf, &prm, NULL, g_rgb, g_d, sil, gc, go, gr, tw, mag) < 0) return 8;
+  double *gkd = malloc(sizeof(double) * (size_t)n), gkp[6];
+  if (orc_render_bwd(&view, &kf, &prm, NULL, g_rgb, g_d, sil, gc, go, gr, tw, mag, gkd, gkp, NULL) < 0) return 8;
   orc_values val = {NULL, NULL, NULL, {1e-3, -2e-3, 1e-3, 1e-3, 2e-3, -1e-3}, 1};
   if (orc_render_fwd(&view, &kf, &prm, &val, 0.f, -1, NULL, img, dimg, sil, tf, nc, mg) < 0) return 9;
   double L2 = orc_map_loss(H, W, img, dimg, rgb, depth, 0.8, 0.2, 1.0, g_rgb, g_d);
@@ -78,7 +83,7 @@ int main(int argc, char **argv) {
   printf("ok n=%d K=%lld L1=%.6g L2=%.6g tw0=%.6g\n", n, (long long)K, L1, L2, tw[0]);
   free(pix); free(dep); free(col); free(opa); free(rad); free(rec); free(ranges); free(keys);
   free(vals); free(img); free(dimg); free(sil); free(tf); free(nc); free(mg); free(g_rgb); free(g_d);
-  free(gc); free(go); free(gr); free(mag); free(depth); free(rgb); free(kpose); free(vpose);
+  free(gc); free(go); free(gr); free(mag); free(gkd); free(depth); free(rgb); free(kpose); free(vpose);
   free(intr); free(dims);
   return 0;
 }

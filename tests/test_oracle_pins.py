@@ -293,7 +293,7 @@ def test_gradient_magnitudes(orc):
     P = view.P
     grad = orc.render_bwd(view, [kf], rng.normal(size=(3, P)), rng.normal(size=P),
                           rng.normal(size=P))
-    for name in ("color", "opacity", "radius", "twist"):
+    for name in ("color", "opacity", "radius", "twist", "depth", "kf_pose"):
         m, g = grad["mag"][name], grad[name]
         assert np.all(m >= np.abs(g) * (1 - 1e-12)), name
         assert np.any(m > 2 * np.abs(g)), name      # random upstream does cancel somewhere
@@ -527,3 +527,271 @@ def test_relative_pose_centres_against_fp64(orc):
     my = cam[1] * Xv[1] / Xv[2] + cam[3]
     assert np.abs(rec["mx"][ok] - mx[ok]).max() < 1e-4
     assert np.abs(rec["my"][ok] - my[ok]).max() < 1e-4
+
+
+# ----------------------------------------------------------------------------
+# near-tie alternatives (the tie reading of the cut-off and stop rules): a
+# decision within the exp uncertainty of its threshold may go either way,
+# and the oracle evaluates the other outcome one decision at a time
+# ----------------------------------------------------------------------------
+
+def test_alternatives_stop_tie_closed_form(orc):
+    """Three opaque layers on one pixel: after the first, T = 1 - 0.99f; the
+    second would take T to (1 - 0.99f)^2 = 1e-4 (1 - 1.9e-6), within the
+    stop uncertainty of t_min, so the stop is a near-tie.  Its other outcome
+    composites the second layer -- the two-layer closed form -- and the third
+    layer then stops (T would fall to ~1e-6, no tie)."""
+    kfs = [one_gaussian_kf(orc, 32, 24, z, color=(c, 0, 0), opacity=0.99)
+           for z, c in ((1.0, 1.0), (1.5, 0.5), (2.0, 0.25))]
+    view = orc.ViewSpec(CAM, IDENT, 0, 3)
+    p = 24 * 64 + 32
+    out = orc.render(view, kfs)
+    assert out["marginal_kind"][p] == 4 and out["n_contrib"][p] == 1
+    alt = orc.render_alternatives(view, kfs, [p])
+    assert alt["n_dec"][0] == 1
+    a = float(np.float32(0.99))
+    assert abs(alt["rgb"][0, 0, 0] - (a + 0.5 * a * (1 - a))) < 1e-12
+    assert abs(alt["depth"][0, 0] - (1.0 * a + 1.5 * a * (1 - a))) < 1e-12
+    assert abs(alt["sil"][0, 0] - (1 - (1 - a) ** 2)) < 1e-12
+    # an unflagged pixel has no alternative
+    far = orc.render_alternatives(view, kfs, [0])
+    assert far["n_dec"][0] == 0 and np.isnan(far["rgb"][0]).all()
+
+
+def test_alternatives_cutoff_tie_closed_form(orc):
+    """Single on-axis sphere (sigma^2 = 1.3): at offset (3, 2), q = 10.0, which
+    a 10 % margin puts within reach of Q_CUT = 11.0826 while alpha = 0.99
+    e^-5 is well above 1/255 -- a candidate near-tie whose other outcome is
+    the empty pixel.  At (4, 0), q = 12.31 is 11 % above the cut: no tie at
+    10 %, and none at 20 % either, since alpha = 0.99 e^-6.15 = 0.0021 is then
+    far below 1/255 and the q test alone cannot change the outcome."""
+    kf = one_gaussian_kf(orc, 32, 24, 2.0, color=(0.3, 0.6, 0.9), opacity=0.99)
+    view = orc.ViewSpec(CAM, IDENT)
+    p_tie, p_out = (24 + 2) * 64 + 32 + 3, 24 * 64 + 36
+    out = orc.render(view, [kf], margin=0.1)
+    assert out["marginal_kind"][p_tie] == 1 and out["marginal_kind"][p_out] == 0
+    a = 0.99 * math.exp(-13 / (2 * 1.3))
+    assert abs(out["sil"][p_tie] - a) < 1e-6
+    alt = orc.render_alternatives(view, [kf], [p_tie, p_out], margin=0.1)
+    assert list(alt["n_dec"]) == [1, 0]
+    assert alt["sil"][0, 0] == 0.0 and alt["depth"][0, 0] == 0.0
+    assert np.all(alt["rgb"][0, 0] == 0.0)
+    # q within 20 % of the cut with alpha far below alpha_min: no tie
+    out2 = orc.render(view, [kf], margin=0.2)
+    assert out2["marginal_kind"][p_out] == 0 and out2["marginal_kind"][p_tie] == 1
+
+
+def test_alternatives_agree_with_flags_on_a_room(orc):
+    """On a generated room under a wide margin: a pixel has alternatives
+    exactly when render() flags a candidate or stop near-tie; every variant
+    is a valid composite (silhouette in [0, 1], depth / silhouette inside the
+    scene's depth range); and most variants differ from the primary result
+    (a flipped candidate that lies behind the pixel's stop changes nothing)."""
+    fr, kf, view = small_room(orc)
+    kfs = [kf]
+    m = 1e-3
+    out = orc.render(view, kfs, margin=m)
+    kind = out["marginal_kind"]
+    fl = np.nonzero(kind)[0]
+    assert fl.size > 10
+    alt = orc.render_alternatives(view, kfs, fl, margin=m, max_alt=8)
+    assert np.array_equal(alt["n_dec"] > 0, (kind[fl] & 5) != 0)
+    zmin, zmax = float(kf.depth.min()) * 0.5, float(kf.depth.max()) * 2.0
+    differ = total = 0
+    for i, p in enumerate(fl):
+        for j in range(min(int(alt["n_dec"][i]), 8)):
+            v = np.concatenate([alt["rgb"][i, j], [alt["depth"][i, j], alt["sil"][i, j]]])
+            w = np.concatenate([out["rgb"][:, p], [out["depth"][p], out["sil"][p]]])
+            s_ = alt["sil"][i, j]
+            assert 0.0 <= s_ <= 1.0
+            if s_ > 1e-3:
+                assert zmin <= alt["depth"][i, j] / s_ <= zmax
+            differ += int(np.abs(v - w).max() > 0.0)
+            total += 1
+    assert differ >= total // 2
+
+
+# ----------------------------------------------------------------------------
+# geometry gradients: each Gaussian's tied depth (the supplementary's
+# Gaussians movable along the ray) and each keyframe's pose (Sec. 3.5
+# bundle adjustment through the tied Gaussians' centres)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("thresholds", ["on", "off"])
+def test_depth_and_keyframe_pose_gradients_finite_differences(orc, thresholds):
+    """Central differences in FP64 of the tied depths and of left twists of
+    both keyframe poses of a two-keyframe slice, against render_bwd."""
+    from paper_2506_02741_amd import synth
+    rng = np.random.default_rng(21)
+    w, h = 24, 18
+    scene = synth.make_room(21)
+    cam = synth.Camera(w * 525.0 / 640, w * 525.0 / 640, w / 2, h / 2, w, h)
+    poses = synth.random_walk(scene, cam, rng, 2)
+    kfs = [orc.ingest(f.depth, f.rgb, fx=cam.fx, cam=cam.as_tuple(), pose=f.pose)
+           for f in (synth.frame(scene, cam, T) for T in poses)]
+    vpose = synth.perturb_pose(poses[0], rng, 0.03, 2.0).astype(np.float32)
+    view = orc.ViewSpec(cam.as_tuple(), vpose, 0, 2)
+    prm = orc.params() if thresholds == "on" else orc.params(alpha_min=0.0, t_min=0.0, q_cut=1e4)
+    if thresholds == "off":
+        for k in kfs:
+            k.opacity[:] = 0.5
+    P = view.P
+    g = (rng.normal(size=(3, P)), rng.normal(size=P), rng.normal(size=P))
+    grad = orc.render_bwd(view, kfs, g[0], g[1], g[2], prm, geometry64=True)
+    d0 = np.concatenate([k.depth for k in kfs]).astype(np.float64)
+    for i in rng.choice(d0.size, 6, replace=False):
+        eps = 1e-7
+        hi = d0.copy(); lo = d0.copy()
+        hi[i] += eps; lo[i] -= eps
+        fd = (_loss(orc, view, kfs, g, prm, depth=hi) - _loss(orc, view, kfs, g, prm, depth=lo)) / (2 * eps)
+        an = grad["depth"][i]
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (i, fd, an)
+    for s in range(2):
+        for k in range(6):
+            eps = 1e-7
+            e = np.zeros((2, 6)); e[s, k] = eps
+            fd = (_loss(orc, view, kfs, g, prm, kf_twist=e) - _loss(orc, view, kfs, g, prm, kf_twist=-e)) / (2 * eps)
+            an = grad["kf_pose"][s, k]
+            assert abs(fd - an) <= 1e-5 * max(abs(an), 1.0), (s, k, fd, an)
+
+
+def test_keyframe_pose_gradient_cancels_view_twist_at_own_pose(orc):
+    """A keyframe's Gaussians seen from that keyframe's own pose: moving the
+    keyframe and the camera by the same left twist changes nothing
+    (T_v T_k^-1 = I stays I), so the keyframe-pose gradient is exactly minus
+    the view twist gradient -- nothing but the other slices carries a bundle
+    adjustment signal (Sec. 3.5).  The view twist is pinned on its own
+    (closed forms, finite differences); this fixes the sign and frame of the
+    keyframe side."""
+    fr, kf, view = small_room(orc, seed=13, perturb=False)
+    rng = np.random.default_rng(2)
+    P = view.P
+    grad = orc.render_bwd(view, [kf], rng.normal(size=(3, P)), rng.normal(size=P), rng.normal(size=P))
+    tw, kp = grad["twist"], grad["kf_pose"][0]
+    assert np.abs(tw).max() > 1.0
+    # (the float32 pose's rotation is orthonormal only to ~1e-7, so T_v T_k^-1
+    # is the identity only to that order)
+    assert np.allclose(kp, -tw, rtol=0, atol=1e-6 * np.abs(tw).max())
+
+
+def test_depth_gradient_is_the_ray_component_of_the_centre_gradient(orc):
+    """Single on-axis sphere at identity pose: its ray is the optical axis,
+    so dL/d(depth) equals the z component of dL/dp, which is the translation
+    twist's z component (dp/drho = I), and moving the keyframe by +rho_z
+    (left twist on world->camera) moves the centre by -rho_z in the view."""
+    kf = one_gaussian_kf(orc, 32, 24, 2.0, opacity=0.8)
+    view = orc.ViewSpec(CAM, IDENT)
+    P = 64 * 48
+    rng = np.random.default_rng(4)
+    grad = orc.render_bwd(view, [kf], rng.normal(size=(3, P)), rng.normal(size=P), None,
+                          geometry64=True)
+    assert abs(grad["depth"][0] - grad["twist"][2]) <= 1e-12 * max(1.0, abs(grad["twist"][2]))
+    assert abs(grad["kf_pose"][0, 2] + grad["twist"][2]) <= 1e-12 * max(1.0, abs(grad["twist"][2]))
+
+
+# ----------------------------------------------------------------------------
+# visibility check (Sec. 3.3): a point is visible to a view when its depth
+# there is within 1 % of the view's depth map, bilinearly interpolated at
+# its projection; the overlap selection's first stage (Sec. 3.3, App. A N1
+# and gamma)
+# ----------------------------------------------------------------------------
+
+def _plane(depth, W=64, H=48):
+    return np.full((H, W), depth, np.float32)
+
+
+def test_visibility_plane_threshold_closed_form(orc):
+    """Fronto-parallel plane at 3 m seen from identity poses: a target depth
+    map of 3 (1 + e) holds every interior point for e = 0.9 % and none for
+    e = 1.1 % (|3 - 3(1+e)| vs 0.01 * 3(1+e)); a target map 0.5 m nearer
+    (something in front) hides every point; the last row and column have no
+    bilinear neighbourhood."""
+    src = _plane(3.0)
+    cam = CAM
+    for e, expect in ((0.009, True), (0.011, False)):
+        vis, counts = orc.visibility(src, cam, IDENT, [(_plane(3.0 * (1 + e)), cam, IDENT)])
+        v = vis[0].reshape(48, 64)
+        assert v[:-1, :-1].all() if expect else not v[:-1, :-1].any()
+        assert not v[-1, :].any() and not v[:, -1].any()
+        assert counts[0] == v.sum()
+    vis, counts = orc.visibility(src, cam, IDENT, [(_plane(2.5), cam, IDENT)])
+    assert counts[0] == 0
+
+
+def test_visibility_occluder_and_out_of_view(orc):
+    """A box 1 m in front of the plane in the target's depth map hides the
+    points behind it (interior of the box region), the rest stays visible;
+    a target turned half way round sees nothing; an invalid (0) depth in a
+    neighbourhood makes the point invisible; points with no depth are never
+    visible."""
+    src = _plane(3.0)
+    tgt = _plane(3.0)
+    tgt[10:30, 20:40] = 1.0
+    tgt[40, 5] = 0.0
+    vis, counts = orc.visibility(src, CAM, IDENT, [(tgt, CAM, IDENT)])
+    v = vis[0].reshape(48, 64)
+    assert not v[11:29, 21:39].any()
+    assert v[:8, :63].all() and v[32:39, 42:63].all()
+    assert not v[39:41, 4:6].any()          # neighbourhoods of the hole
+    src2 = src.copy(); src2[0, 0] = 0.0
+    away = np.concatenate([np.diag([-1.0, 1.0, -1.0]), np.zeros((3, 1))], 1).astype(np.float32)
+    vis2, counts2 = orc.visibility(src2, CAM, IDENT, [(tgt, CAM, away), (src, CAM, IDENT)])
+    assert counts2[0] == 0 and not vis2[1][0]
+
+
+def test_visibility_against_fp64_brute_force(orc):
+    """A generated room seen from a second pose along a walk: the FP32
+    decisions equal an independent FP64 evaluation (numpy, poses composed in
+    FP64) wherever the FP64 margins are clear of the 1 % threshold and of the
+    pixel grid lines (where the rounding of the projection can change the
+    bilinear cell)."""
+    from paper_2506_02741_amd import synth
+    rng = np.random.default_rng(41)
+    w, h = 96, 72
+    scene = synth.make_room(41)
+    cam = synth.Camera(w * 525.0 / 640, w * 525.0 / 640, w / 2, h / 2, w, h)
+    poses = synth.random_walk(scene, cam, rng, 3, step=0.3, rot_deg=10.0)
+    frames = [synth.frame(scene, cam, T) for T in poses]
+    src, tgts = frames[0], frames[1:]
+    vis, counts = orc.visibility(src.depth, cam.as_tuple(), src.pose,
+                                 [(f.depth, cam.as_tuple(), f.pose) for f in tgts])
+    Ts = np.asarray(src.pose, np.float64).reshape(3, 4)
+    v_, u_ = np.mgrid[0:h, 0:w]
+    d = src.depth.astype(np.float64)
+    n = np.stack([(u_ - cam.cx) / cam.fx, (v_ - cam.cy) / cam.fy, np.ones_like(d)])
+    Xs = n * d
+    Xw = np.einsum("ji,jhw->ihw", Ts[:, :3], Xs - Ts[:, 3][:, None, None])
+    checked = 0
+    for t, f in enumerate(tgts):
+        Tt = np.asarray(f.pose, np.float64).reshape(3, 4)
+        p = np.einsum("ij,jhw->ihw", Tt[:, :3], Xw) + Tt[:, 3][:, None, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            mx = cam.fx * p[0] / p[2] + cam.cx
+            my = cam.fy * p[1] / p[2] + cam.cy
+        D = f.depth.astype(np.float64)
+        ok = (d > 0) & (p[2] > 0.01) & (mx >= 0) & (my >= 0) & (mx < w - 1) & (my < h - 1)
+        x0 = np.clip(np.floor(np.where(ok, mx, 0)), 0, w - 2).astype(int)
+        y0 = np.clip(np.floor(np.where(ok, my, 0)), 0, h - 2).astype(int)
+        d00, d01, d10, d11 = D[y0, x0], D[y0, x0 + 1], D[y0 + 1, x0], D[y0 + 1, x0 + 1]
+        ok &= (d00 > 0) & (d01 > 0) & (d10 > 0) & (d11 > 0)
+        ax, ay = mx - x0, my - y0
+        Dt = (1 - ay) * ((1 - ax) * d00 + ax * d01) + ay * ((1 - ax) * d10 + ax * d11)
+        ref = ok & (np.abs(p[2] - Dt) <= 0.01 * Dt)
+        frac = lambda z: np.minimum(z - np.floor(z), np.ceil(z) - z)
+        clear = (np.abs(np.abs(p[2] - Dt) - 0.01 * Dt) > 1e-4 * Dt) & (frac(mx) > 1e-3) & \
+            (frac(my) > 1e-3) & (np.abs(mx - (w - 1)) > 1e-3) & (np.abs(my - (h - 1)) > 1e-3)
+        got = vis[t].reshape(h, w)
+        assert np.array_equal(got[clear], ref[clear])
+        assert 0.05 < ref.mean() < 0.95
+        checked += int(clear.sum())
+    assert checked > 0.9 * 2 * w * h
+
+
+def test_overlap_selection_rule(orc):
+    """Candidates above gamma of the valid points; the three most front
+    (earliest) sections holding one of them, each once."""
+    counts = [10, 800, 900, 300, 700, 650, 100]
+    sections = [0, 1, 1, 2, 3, 4, 5]
+    assert orc.select_overlap(counts, 1000, sections, 0.26) == [1, 2, 3]
+    assert orc.select_overlap(counts, 1000, sections, 0.68) == [1, 3]
+    assert orc.select_overlap(counts, 1000, sections, 0.95) == []

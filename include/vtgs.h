@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define VTGS_ABI_VERSION 1
+#define VTGS_ABI_VERSION 2
 
 typedef enum {
   VTGS_OK = 0,
@@ -75,11 +75,14 @@ typedef struct {
 typedef struct {
   int32_t n;                 /* number of Gaussians                          */
   const uint32_t *pix;       /* device [n] row-major pixel index in the keyframe */
-  const float *depth;        /* device [n] z-depth of that pixel (m), > 0     */
+  float *depth;              /* device [n] z-depth of that pixel (m), > 0: the
+                                Gaussian's place on its pixel's ray; map_step
+                                moves it when depth_adam != NULL              */
   float *color;              /* device [3][n] planar colour c                 */
   float *opacity;            /* device [n] opacity o in (0, 1]                */
   float *radius;             /* device [n] radius r (m), > 0                  */
-  const float *pose;         /* device [12] world->camera of the keyframe     */
+  float *pose;               /* device [12] world->camera of the keyframe;
+                                map_step adjusts it when pose_adam != NULL    */
   vtgs_camera cam;           /* keyframe intrinsics and image size            */
   int32_t learnable;         /* 1: receives gradients / optimiser steps       */
   float *g_color;            /* device [3][n], render_bwd adds (+=); or NULL  */
@@ -87,6 +90,18 @@ typedef struct {
   float *g_radius;           /* device [n], or NULL                           */
   float *adam;               /* device [10][n]: Adam m[5], v[5] over
                                 (c0,c1,c2, logit o, log r) for map_step; or NULL */
+  /* Geometry of a learnable keyframe (supplementary: Gaussians movable
+   * along the ray; Sec. 3.5: bundle adjustment of a keyframe pose through
+   * its tied Gaussians' centres).  Any of them non-NULL makes the backward
+   * also carry dLoss/d(centre) per Gaussian. */
+  float *g_depth;            /* device [n], render_bwd adds dLoss/d(depth) (+=); or NULL */
+  float *g_pose;             /* device [6], render_bwd adds dLoss/d(xi) of a left
+                                twist xi = (rho, phi) of the pose, pose <-
+                                exp(xi^) pose, at xi = 0 (+=); or NULL         */
+  float *depth_adam;         /* device [2][n]: Adam m, v of the depth for map_step; or NULL */
+  float *pose_adam;          /* device [13]: Adam m[6], v[6], t of the pose twist for
+                                map_step (lr_trans on rho, lr_rot on phi, then
+                                pose <- exp(step^) pose); or NULL              */
 } vtgs_keyframe;
 
 /* One rendered view: keyframes [kf_first, kf_first + kf_count) of the
@@ -117,8 +132,12 @@ typedef struct {
  * threshold of the mask W (default 0.5). */
 typedef struct { float alpha, beta, lr_rot, lr_trans, sil_thr; } vtgs_track_cfg;
 
-/* Eq. 2 weights and learning rates of colour, opacity, radius (App. A). */
-typedef struct { float rho, tau, sigma, lr_color, lr_opacity, lr_radius; } vtgs_map_cfg;
+/* Eq. 2 weights and learning rates of colour, opacity, radius (App. A), of
+ * the tied depths of keyframes with depth_adam, and of the poses of
+ * keyframes with pose_adam (translation, rotation). */
+typedef struct {
+  float rho, tau, sigma, lr_color, lr_opacity, lr_radius, lr_depth, lr_trans, lr_rot;
+} vtgs_map_cfg;
 
 typedef struct vtgs_plan vtgs_plan;
 
@@ -146,6 +165,17 @@ int vtgs_ingest_fill(const float *depth_img, const float *rgb_img, const uint8_t
                      int32_t H, int32_t W, int32_t stride, float fx, float o_init,
                      const void *scratch, int64_t scratch_bytes, int32_t n, uint32_t *pix,
                      float *depth, float *color, float *opacity, float *radius, void *stream);
+
+/* ---- complement initialisation [Sec. 3.4] ---------------------------------
+ * mask[p] = 1 where the current Gaussians leave pixel p of a frame
+ * uncovered -- the silhouette of their rendering at the frame's pose,
+ * sil[p] (device [n]), below thr (the paper's 0.5) -- and the frame's depth
+ * depth_img[p] (device [n]) is valid (> 0 and finite); else 0.  Passed to
+ * vtgs_ingest_count / vtgs_ingest_fill as their mask, it ties new
+ * Gaussians to exactly those pixels.  mask: device uint8 [n].  VTGS_E_ARG
+ * for NULL arrays or n < 0, nothing enqueued. */
+int vtgs_uncovered_mask(const float *sil, const float *depth_img, int64_t n, float thr,
+                        uint8_t *mask, void *stream);
 
 /* ---- plans --------------------------------------------------------------
  * A plan fixes a batch of views over an array of keyframes (host copies of
@@ -184,10 +214,12 @@ int vtgs_render_fwd(vtgs_plan *plan, float *rgb, float *depth, float *sil, void 
 /* ---- render_bwd: gradients of a scalar loss through the last render_fwd --
  * g_rgb [3][P], g_depth [P], g_sil [P]: dLoss/d(outputs), device, NULL = 0.
  * Adds dLoss/dc, dLoss/do, dLoss/dr into g_color/g_opacity/g_radius of every
- * learnable keyframe that has them, summed over views [Sec. 3.4]; writes
- * dLoss/dxi [n_views][6] into g_twist (device, or NULL) where xi = (rho, phi)
- * is a left twist of each view's world->camera pose, pose <- exp(xi^) pose,
- * taken at xi = 0 [Sec. 3.3]. */
+ * learnable keyframe that has them, summed over views [Sec. 3.4], and
+ * dLoss/d(depth) and the keyframe pose twist gradient into g_depth / g_pose
+ * where given [Sec. 3.5; supplementary, Gaussians movable along the ray];
+ * writes dLoss/dxi [n_views][6] into g_twist (device, or NULL) where
+ * xi = (rho, phi) is a left twist of each view's world->camera pose,
+ * pose <- exp(xi^) pose, taken at xi = 0 [Sec. 3.3]. */
 int vtgs_render_bwd(vtgs_plan *plan, const float *g_rgb, const float *g_depth,
                     const float *g_sil, float *g_twist, void *stream);
 
@@ -208,9 +240,39 @@ int vtgs_track_step(vtgs_plan *plan, const vtgs_track_cfg *cfg, int32_t iters, f
  * losses, back-propagates to c, o, r of the learnable keyframes and takes
  * one Adam step on (c, logit o, log r) with lr_color, lr_opacity, lr_radius
  * (state in keyframe.adam, step counter *step on the device, incremented).
- * loss: device [n_views] (or NULL). */
+ * A learnable keyframe with depth_adam also moves its Gaussians along their
+ * rays (Adam on depth, lr_depth), and one with pose_adam adjusts its pose
+ * (Adam on a left twist, lr_trans / lr_rot, then pose <- exp(step^) pose;
+ * its own step count in pose_adam[12]) [Sec. 3.5].  The centres move only
+ * from the next iteration on.  loss: device [n_views] (or NULL). */
 int vtgs_map_step(vtgs_plan *plan, const vtgs_map_cfg *cfg, int32_t *step, float *loss,
                   void *stream);
+
+/* ---- visibility check [Sec. 3.3] ----------------------------------------
+ * A frame to test against: its depth map (device [H*W], 0 = invalid), its
+ * intrinsics and image size, and its world->camera pose (device [12]). */
+typedef struct {
+  const float *depth;
+  vtgs_camera cam;
+  const float *pose;
+} vtgs_frame_ref;
+
+/* The point of source pixel (u, v) with depth d > 0 (back-projected with
+ * src_cam at src_pose) is visible in a target when its depth in the target
+ * camera, p_z > z_near, lies within rel_tol (the paper's 1 %: 0.01) of the
+ * target's depth map bilinearly interpolated at its projection, the four
+ * neighbours inside the map and valid.  FP32 in a fixed operation order,
+ * the back-projection and projection being those of the splat's records.
+ * mask: device [H*W] of the source, 1 where the point is visible in at
+ * least one target (the union Eq. 1's W takes over a section's head, middle
+ * and last frames), or NULL.  counts: device int32 [n_targets], the visible
+ * points per target (the overlap selection), or NULL.  Targets may have
+ * other resolutions than the source.  Asynchronous on `stream`; argument
+ * errors (NULL source or target arrays, bad cameras, n_targets < 1,
+ * rel_tol < 0) return VTGS_E_ARG with nothing enqueued. */
+int vtgs_visibility(const float *src_depth, const vtgs_camera *src_cam, const float *src_pose,
+                    const vtgs_frame_ref *targets, int32_t n_targets, float rel_tol, float z_near,
+                    uint8_t *mask, int32_t *counts, void *stream);
 
 /* ---- measurement ----------------------------------------------------------
  * Stage timing: enable != 0 starts recording HIP events on the call's stream
@@ -242,11 +304,12 @@ int vtgs_debug_state(vtgs_plan *plan, float *records, int32_t *rect, uint32_t *r
  * Either pointer may be NULL. */
 int vtgs_debug_images(vtgs_plan *plan, float *img, float *gimg, void *stream);
 
-/* Adds, on `stream`, the per-Gaussian gradients (colour, opacity, radius)
- * that the last backward to colour/opacity/radius left in the workspace --
- * the values map_step's Adam step used -- into g_color, g_opacity and
- * g_radius of every learnable keyframe that has them.  VTGS_E_ARG when the
- * plan has no learnable keyframe or no such backward ran on it yet. */
+/* Adds, on `stream`, the per-Gaussian gradients (colour, opacity, radius,
+ * and depth and the keyframe pose twist when the plan carries geometry) that
+ * the last backward to colour/opacity/radius left in the workspace -- the
+ * values map_step's Adam step used -- into g_color, g_opacity, g_radius,
+ * g_depth and g_pose of every learnable keyframe that has them.  VTGS_E_ARG
+ * when the plan has no learnable keyframe or no such backward ran on it yet. */
 int vtgs_debug_gather(vtgs_plan *plan, void *stream);
 
 #ifdef __cplusplus

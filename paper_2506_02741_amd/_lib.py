@@ -12,6 +12,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvtgs.so")
 
+VTGS_ABI_VERSION = 2  # the structures below follow this version of vtgs.h
 VTGS_OK = 0
 VTGS_E_ARG = -1
 VTGS_E_HIP = -2
@@ -31,13 +32,18 @@ class vtgs_keyframe(C.Structure):
                 ("color", C.c_void_p), ("opacity", C.c_void_p), ("radius", C.c_void_p),
                 ("pose", C.c_void_p), ("cam", vtgs_camera), ("learnable", C.c_int32),
                 ("g_color", C.c_void_p), ("g_opacity", C.c_void_p), ("g_radius", C.c_void_p),
-                ("adam", C.c_void_p)]
+                ("adam", C.c_void_p), ("g_depth", C.c_void_p), ("g_pose", C.c_void_p),
+                ("depth_adam", C.c_void_p), ("pose_adam", C.c_void_p)]
 
 
 class vtgs_view(C.Structure):
     _fields_ = [("cam", vtgs_camera), ("pose", C.c_void_p), ("kf_first", C.c_int32),
                 ("kf_count", C.c_int32), ("obs_rgb", C.c_void_p), ("obs_depth", C.c_void_p),
                 ("vis", C.c_void_p), ("pose_adam", C.c_void_p)]
+
+
+class vtgs_frame_ref(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("cam", vtgs_camera), ("pose", C.c_void_p)]
 
 
 class vtgs_params(C.Structure):
@@ -53,7 +59,8 @@ class vtgs_track_cfg(C.Structure):
 
 class vtgs_map_cfg(C.Structure):
     _fields_ = [("rho", C.c_float), ("tau", C.c_float), ("sigma", C.c_float),
-                ("lr_color", C.c_float), ("lr_opacity", C.c_float), ("lr_radius", C.c_float)]
+                ("lr_color", C.c_float), ("lr_opacity", C.c_float), ("lr_radius", C.c_float),
+                ("lr_depth", C.c_float), ("lr_trans", C.c_float), ("lr_rot", C.c_float)]
 
 
 _P = C.c_void_p
@@ -70,6 +77,7 @@ SIGNATURES = {
     "vtgs_ingest_count": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "vtgs_ingest_fill": (C.c_int, [_P, _P, _P, _I32, _I32, _I32, _F, _F, _P, _I64, _I32, _P, _P,
                                    _P, _P, _P, _P]),
+    "vtgs_uncovered_mask": (C.c_int, [_P, _P, _I64, _F, _P, _P]),
     "vtgs_plan_create": (C.c_int, [_P, _I32, _P, _I32, _P, _I64, _P]),
     "vtgs_plan_destroy": (None, [_P]),
     "vtgs_plan_workspace_bytes": (_I64, [_P]),
@@ -87,6 +95,7 @@ SIGNATURES = {
     "vtgs_debug_state": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "vtgs_debug_images": (C.c_int, [_P, _P, _P, _P]),
     "vtgs_debug_gather": (C.c_int, [_P, _P]),
+    "vtgs_visibility": (C.c_int, [_P, _P, _P, _P, _I32, _F, _F, _P, _P, _P]),
     "vtgs_stage_name": (C.c_char_p, [_I32]),
     "vtgs_plan_timing": (C.c_int, [_P, _I32, _P, _P]),
 }
@@ -112,6 +121,9 @@ def load():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.vtgs_abi_version() != VTGS_ABI_VERSION:
+            raise ImportError("libvtgs.so has ABI version %d, the binding expects %d (rebuild)"
+                              % (L.vtgs_abi_version(), VTGS_ABI_VERSION))
         _lib = L
     return _lib
 

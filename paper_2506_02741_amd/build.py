@@ -21,13 +21,14 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvtgs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.cpp", "k_ingest.hip", "k_binning.hip", "k_composite.hip", "k_optim.hip"]
+SOURCES = ["abi.cpp", "k_ingest.hip", "k_binning.hip", "k_composite.hip", "k_optim.hip",
+           "k_visibility.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-fast-math",
           "-Wno-unused-command-line-argument",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-PER_FILE = {"k_binning.hip": ["-ffp-contract=off"]}
+PER_FILE = {"k_binning.hip": ["-ffp-contract=off"], "k_visibility.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

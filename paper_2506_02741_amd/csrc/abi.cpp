@@ -86,11 +86,13 @@ struct vtgs_plan {
   int32_t n_rec = 0, n_tiles = 0, loss_blocks = 0, ssim_gx = 0, ssim_gy = 0;
   int32_t max_learn_n = 0;
   bool any_learnable = false;
+  bool any_geo = false;  // a learnable keyframe wants depth / pose gradients
   // workspace layout
   Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
-      r_ranges, r_long, r_keys, r_keys_tmp, r_ids, r_slots, r_bits, r_tfinal, r_last, r_img,
-      r_gimg, r_twist, r_loss, r_ssim_map, r_ssim_part;
+      r_ranges, r_long, r_keys, r_keys_tmp, r_ids, r_slots, r_kpose, r_bits, r_tfinal, r_last,
+      r_img, r_gimg, r_twist, r_loss, r_ssim_map, r_ssim_part;
   int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
+  std::vector<char> desc_host;  // the descriptor tables as laid out in the workspace
   int64_t ws_bytes = 0;
   // binding
   char *ws = nullptr;
@@ -130,6 +132,12 @@ int validate_cam(const vtgs_camera &c, const char *what, int idx) {
   return VTGS_OK;
 }
 
+// Floats per (record, tile) gradient slot: dL/dc (3), dL/do, dL/dr, and with
+// geometry dL/dp (3).
+int64_t slot_width(const vtgs_plan *p) { return p->any_geo ? 8 : 5; }
+// Blocks of the per-Gaussian gather over the largest learnable keyframe.
+int64_t gather_blocks(const vtgs_plan *p) { return (p->max_learn_n + 255) / 256; }
+
 void layout(vtgs_plan *p) {
   int64_t off = 0;
   auto take = [&](Region &r, int64_t bytes) {
@@ -161,7 +169,8 @@ void layout(vtgs_plan *p) {
   take(p->r_keys, cap * 8);
   take(p->r_keys_tmp, cap * 8);
   take(p->r_ids, cap * 4);
-  take(p->r_slots, p->any_learnable ? cap * 20 : 0);
+  take(p->r_slots, p->any_learnable ? cap * 4 * slot_width(p) : 0);
+  take(p->r_kpose, p->any_geo ? nk * gather_blocks(p) * 32 : 0);
   // per 64-entry chunk of a tile list: each lane's bit mask of the entries
   // that reach its pixel(s), written by the forward, read by the backward
   take(p->r_bits, (cap / 64 + nt + 2) * (int64_t)lane_bits_per_chunk(p->prm.tile) * 8);
@@ -171,7 +180,7 @@ void layout(vtgs_plan *p) {
   take(p->r_gimg, 5 * P * 4);
   take(p->r_twist, nt * 32);
   take(p->r_loss, nv * (int64_t)p->loss_blocks * 16);
-  take(p->r_ssim_map, 9 * P * 4);
+  take(p->r_ssim_map, 9 * P * 8);
   take(p->r_ssim_part, nv * 3 * (int64_t)p->ssim_gx * p->ssim_gy * 4);
   p->ws_bytes = off;
 }
@@ -216,6 +225,9 @@ void make_ws(vtgs_plan *p) {
   w.keys_tmp = at<unsigned long long>(b, p->r_keys_tmp);
   w.ids = at<uint32_t>(b, p->r_ids);
   w.slots = p->any_learnable ? at<float>(b, p->r_slots) : nullptr;
+  w.kpose_part = p->any_geo ? at<float>(b, p->r_kpose) : nullptr;
+  w.slot_w = (int32_t)slot_width(p);
+  w.gblocks = (int32_t)gather_blocks(p);
   w.lane_bits = at<unsigned long long>(b, p->r_bits);
   w.t_final = at<float>(b, p->r_tfinal);
   w.last = at<uint32_t>(b, p->r_last);
@@ -223,7 +235,7 @@ void make_ws(vtgs_plan *p) {
   w.gimg = at<float>(b, p->r_gimg);
   w.twist_part = at<float>(b, p->r_twist);
   w.loss_part = at<float>(b, p->r_loss);
-  w.ssim_map = at<float>(b, p->r_ssim_map);
+  w.ssim_map = at<double>(b, p->r_ssim_map);
   w.ssim_part = at<float>(b, p->r_ssim_part);
   w.loss_blocks = p->loss_blocks;
   w.ssim_gx = p->ssim_gx;
@@ -237,6 +249,17 @@ void make_ws(vtgs_plan *p) {
   for (int c = 0; c < 3; c++) w.bg[c] = p->prm.bg[c];
   w.tile = p->prm.tile;
   w.batch = p->prm.batch;
+}
+
+// The descriptor tables in their workspace layout, kept on the host.
+void desc_image(vtgs_plan *p) {
+  p->desc_host.assign((size_t)std::max<int64_t>(p->desc_bytes, 256), 0);
+  char *h = p->desc_host.data();
+  if (!p->kfs.empty()) std::memcpy(h + p->desc_kf, p->kfs.data(), p->kfs.size() * sizeof(DevKF));
+  std::memcpy(h + p->desc_view, p->views.data(), p->views.size() * sizeof(DevView));
+  if (!p->segs.empty()) std::memcpy(h + p->desc_seg, p->segs.data(), p->segs.size() * sizeof(DevSeg));
+  std::memcpy(h + p->desc_use_off, p->kf_use_off.data(), p->kf_use_off.size() * 4);
+  if (!p->kf_use.empty()) std::memcpy(h + p->desc_use, p->kf_use.data(), p->kf_use.size() * sizeof(DevKFUse));
 }
 
 int check_bound(vtgs_plan *p) {
@@ -310,6 +333,26 @@ int track_iteration(vtgs_plan *p, const vtgs_track_cfg &cfg, float *loss, hipStr
   // Eq. 1 and its upstream gradient are evaluated by the backward per pixel
   STAGE(p, ST_BWD, st, launch_composite_bwd(w, nullptr, nullptr, nullptr, 1, st, &cfg));
   STAGE(p, ST_UPDATE, st, launch_track_update(w, cfg, loss, st));
+  return VTGS_OK;
+}
+
+// Point the plan at workspace `ws`: upload the descriptor tables from the
+// host copy `h` (pinned, or the plan's own), clear the header and the tile
+// counters, and drop graphs captured against the previous binding.
+int bind_to(vtgs_plan *p, char *ws, const char *h, hipStream_t st) {
+  if (!p->upload_done) HIP_OK(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming));
+  p->ws = ws;
+  make_ws(p);
+  for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+  HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(p->upload_done, st));
+  HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
+  HIP_OK(launch_fill_u32(p->w.tile_count, 0u, p->n_tiles, st));
+  HIP_OK(launch_fill_u32(p->w.tile_fill, 0u, p->n_tiles, st));
+  p->bound = true;
+  p->fwd_done = false;
+  p->slots_done = false;
   return VTGS_OK;
 }
 
@@ -416,10 +459,16 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
       d.fx = K.cam.fx; d.fy = K.cam.fy; d.cx = K.cam.cx; d.cy = K.cam.cy;
       d.width = K.cam.width; d.height = K.cam.height; d.n = K.n; d.learnable = K.learnable ? 1 : 0;
       d.g_color = K.g_color; d.g_opacity = K.g_opacity; d.g_radius = K.g_radius; d.adam = K.adam;
+      if (d.learnable) {
+        d.g_depth = K.g_depth; d.g_pose = K.g_pose;
+        d.depth_adam = K.depth_adam; d.pose_adam = K.pose_adam;
+        d.geo = (K.g_depth || K.g_pose || K.depth_adam || K.pose_adam) ? 1 : 0;
+      }
       p->kfs.push_back(d);
       if (d.learnable && d.n > 0) {
         p->any_learnable = true;
         p->max_learn_n = std::max(p->max_learn_n, d.n);
+        if (d.geo) p->any_geo = true;
       }
     }
     for (int v = 0; v < n_views; v++) {
@@ -472,7 +521,10 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
     p->kf_use.resize(p->segs.size());
     {
       std::vector<int32_t> fill(p->kf_use_off.begin(), p->kf_use_off.end() - 1);
-      for (const DevSeg &s : p->segs) p->kf_use[fill[s.kf]++] = DevKFUse{s.rec_start, s.view};
+      for (size_t i = 0; i < p->segs.size(); i++) {
+        const DevSeg &s = p->segs[i];
+        p->kf_use[fill[s.kf]++] = DevKFUse{s.rec_start, s.view, (int32_t)i};
+      }
     }
     p->n_rec = (int32_t)n_rec;
     p->n_tiles = (int32_t)n_tiles;
@@ -493,6 +545,7 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
     const int64_t cap = std::max<int64_t>(1, (int64_t)std::min(want, (double)kMaxCap));
     p->cap = cap;
     layout(p);
+    desc_image(p);
     *out = p;
     return VTGS_OK;
   } catch (...) {
@@ -510,6 +563,19 @@ void vtgs_plan_destroy(vtgs_plan *p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   delete p;
+}
+
+int vtgs_uncovered_mask(const float *sil, const float *depth_img, int64_t n, float thr,
+                        uint8_t *mask, void *stream) {
+  try {
+    if (n < 0 || (n > 0 && (!sil || !depth_img || !mask)))
+      return fail(VTGS_E_ARG, "uncovered_mask: need n >= 0 and non-NULL arrays");
+    if (!std::isfinite(thr)) return fail(VTGS_E_ARG, "uncovered_mask: thr must be finite");
+    HIP_OK(launch_uncovered(sil, depth_img, n, thr, mask, (hipStream_t)stream));
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "uncovered_mask: unexpected exception");
+  }
 }
 
 int64_t vtgs_plan_workspace_bytes(const vtgs_plan *p) { return p ? p->ws_bytes : -1; }
@@ -537,28 +603,9 @@ int vtgs_plan_bind(vtgs_plan *p, void *ws, int64_t ws_bytes, void *stream) {
       p->pinned = pinned_take((size_t)std::max<int64_t>(p->desc_bytes, 256), &p->pinned_cap);
       if (!p->pinned) return fail(VTGS_E_HIP, "plan_bind: pinned host allocation failed");
     }
-    if (!p->upload_done) HIP_OK(hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming));
     char *h = (char *)p->pinned;
-    std::memset(h, 0, p->desc_bytes);
-    if (!p->kfs.empty()) std::memcpy(h + p->desc_kf, p->kfs.data(), p->kfs.size() * sizeof(DevKF));
-    std::memcpy(h + p->desc_view, p->views.data(), p->views.size() * sizeof(DevView));
-    if (!p->segs.empty()) std::memcpy(h + p->desc_seg, p->segs.data(), p->segs.size() * sizeof(DevSeg));
-    std::memcpy(h + p->desc_use_off, p->kf_use_off.data(), p->kf_use_off.size() * 4);
-    if (!p->kf_use.empty()) std::memcpy(h + p->desc_use, p->kf_use.data(), p->kf_use.size() * sizeof(DevKFUse));
-    p->ws = (char *)ws;
-    make_ws(p);
-    // captured pointers refer to the previous binding
-    for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
-    p->graphs.clear();
-    HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
-    HIP_OK(hipEventRecord(p->upload_done, st));
-    HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
-    HIP_OK(launch_fill_u32(p->w.tile_count, 0u, p->n_tiles, st));
-    HIP_OK(launch_fill_u32(p->w.tile_fill, 0u, p->n_tiles, st));
-    p->bound = true;
-    p->fwd_done = false;
-    p->slots_done = false;
-    return VTGS_OK;
+    std::memcpy(h, p->desc_host.data(), p->desc_bytes);
+    return bind_to(p, (char *)ws, h, st);
   } catch (...) {
     return fail(VTGS_E_HIP, "plan_bind: unexpected exception");
   }
@@ -602,7 +649,10 @@ int vtgs_render_bwd(vtgs_plan *p, const float *g_rgb, const float *g_depth, cons
     bool want_kf = false;
     for (const DevKF &k : p->kfs)
       if (k.learnable && k.n > 0 && (k.g_color || k.g_opacity || k.g_radius)) want_kf = true;
-    const int mode = (g_twist ? 1 : 0) | (want_kf ? 2 : 0);
+    bool want_geo = false;
+    for (const DevKF &k : p->kfs)
+      if (k.learnable && k.n > 0 && (k.g_depth || k.g_pose)) want_geo = true;
+    const int mode = (g_twist ? 1 : 0) | (want_kf || want_geo ? 2 : 0) | (p->any_geo && (want_kf || want_geo) ? 4 : 0);
     if (mode == 0) return VTGS_OK;
     const Ws &w = p->w;
     if (mode & 2) STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
@@ -703,7 +753,8 @@ int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *l
     STAGE(p, ST_LOSS, st, launch_map_loss(w, *cfg, st));
     if (p->any_learnable) {
       STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
-      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr, 2, st));
+      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr,
+                                                 p->any_geo ? 6 : 2, st));
       p->slots_done = true;
     }
     STAGE(p, ST_UPDATE, st,
@@ -711,6 +762,43 @@ int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *l
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "map_step: unexpected exception");
+  }
+}
+
+int vtgs_visibility(const float *src_depth, const vtgs_camera *src_cam, const float *src_pose,
+                    const vtgs_frame_ref *targets, int32_t n_targets, float rel_tol, float z_near,
+                    uint8_t *mask, int32_t *counts, void *stream) {
+  try {
+    if (!src_depth || !src_cam || !src_pose || !targets || n_targets < 1)
+      return fail(VTGS_E_ARG, "visibility: need the source arrays and n_targets >= 1 targets");
+    if (int rc = validate_cam(*src_cam, "visibility source", 0)) return rc;
+    if (!(rel_tol >= 0.f) || !std::isfinite(rel_tol) || !std::isfinite(z_near))
+      return fail(VTGS_E_ARG, "visibility: need a finite rel_tol >= 0 and a finite z_near");
+    for (int t = 0; t < n_targets; t++) {
+      if (!targets[t].depth || !targets[t].pose)
+        return fail(VTGS_E_ARG, "visibility: target " + std::to_string(t) + " has a NULL array");
+      if (int rc = validate_cam(targets[t].cam, "visibility target", t)) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (counts) HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(counts), 0u, n_targets, st));
+    const VisCam sc{src_cam->fx, src_cam->fy, src_cam->cx, src_cam->cy, src_cam->width,
+                    src_cam->height};
+    for (int t0 = 0; t0 < n_targets; t0 += kVisMaxTargets) {
+      VisTargets tg{};
+      tg.n = std::min(kVisMaxTargets, n_targets - t0);
+      for (int j = 0; j < tg.n; j++) {
+        const vtgs_frame_ref &F = targets[t0 + j];
+        tg.depth[j] = F.depth;
+        tg.pose[j] = F.pose;
+        tg.fx[j] = F.cam.fx; tg.fy[j] = F.cam.fy; tg.cx[j] = F.cam.cx; tg.cy[j] = F.cam.cy;
+        tg.width[j] = F.cam.width; tg.height[j] = F.cam.height;
+      }
+      HIP_OK(launch_visibility(src_depth, sc, src_pose, tg, rel_tol, z_near, mask,
+                               counts ? counts + t0 : nullptr, t0 == 0 ? 1 : 0, st));
+    }
+    return VTGS_OK;
+  } catch (...) {
+    return fail(VTGS_E_HIP, "visibility: unexpected exception");
   }
 }
 
@@ -769,7 +857,11 @@ int vtgs_debug_images(vtgs_plan *p, float *img, float *gimg, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes = (size_t)p->P * 5 * sizeof(float);
     if (img) HIP_OK(hipMemcpyAsync(img, p->w.img, bytes, hipMemcpyDeviceToDevice, st));
-    if (gimg) HIP_OK(hipMemcpyAsync(gimg, p->w.gimg, bytes, hipMemcpyDeviceToDevice, st));
+    if (gimg) {
+      // the silhouette plane map_step never forms is reported as zeros
+      HIP_OK(hipMemcpyAsync(gimg, p->w.gimg, bytes * 4 / 5, hipMemcpyDeviceToDevice, st));
+      HIP_OK(launch_fill_f32(gimg + 4 * p->P, 0.f, p->P, st));
+    }
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "debug_images: unexpected exception");

@@ -17,6 +17,7 @@
 // lists are bit-identical to an IEEE single-precision evaluation of the same
 // expressions.
 #include "vtgs_internal.h"
+#include "geom32.h"
 
 #pragma clang fp contract(off)
 
@@ -34,25 +35,6 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
 __global__ void k_fill_f32(float *p, float v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
-}
-
-// M = Tv * Tk^-1 = [Rv Rk^T | tv - (Rv Rk^T) tk], fixed summation order.
-// Relative pose M = T_v T_k^-1 (3x4, world->camera poses with orthonormal
-// rotations, so T_k^-1 = [R_k^T | -R_k^T t_k]) in a fixed FP32 order.
-__device__ __forceinline__ void relative_pose(const float *Tv, const float *Tk, float *M) {
-  float tv[12], tk[12];
-#pragma unroll
-  for (int i = 0; i < 12; i++) { tv[i] = Tv[i]; tk[i] = Tk[i]; }
-#pragma unroll
-  for (int i = 0; i < 3; i++)
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-      M[4 * i + j] = (tv[4 * i + 0] * tk[4 * j + 0] + tv[4 * i + 1] * tk[4 * j + 1]) +
-                     tv[4 * i + 2] * tk[4 * j + 2];
-#pragma unroll
-  for (int i = 0; i < 3; i++)
-    M[4 * i + 3] = tv[4 * i + 3] -
-                   ((M[4 * i + 0] * tk[3] + M[4 * i + 1] * tk[7]) + M[4 * i + 2] * tk[11]);
 }
 
 __device__ __forceinline__ int find_seg(const Ws &ws, int r) {
@@ -151,6 +133,11 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     tiles_x = vw.tiles_x;
     tile_base = vw.tile_base;
     const int i = r - sg.rec_start;
+    // the segment's relative pose, kept for the gradient gathers
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < 12; c++) ws.segs[seg].M[c] = M[c];
+    }
     // every per-Gaussian load issued together, before the arithmetic
     const uint32_t pix = kf.pix[i];
     const float d = kf.depth[i];
@@ -160,13 +147,9 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
                 c2 = kf.color[2 * (int64_t)kf.n + i];
     const float learn = kf.learnable ? 1.f : 0.f;
     const int u = (int)(pix % (uint32_t)kwidth), v = (int)(pix / (uint32_t)kwidth);
-    // back-projection of the tied depth pixel (keyframe camera)
-    const float xk = (((float)u - kcx) / kfx) * d;
-    const float yk = (((float)v - kcy) / kfy) * d;
-    const float zk = d;
-    const float px = ((M[0] * xk + M[1] * yk) + M[2] * zk) + M[3];
-    const float py = ((M[4] * xk + M[5] * yk) + M[6] * zk) + M[7];
-    const float pz = ((M[8] * xk + M[9] * yk) + M[10] * zk) + M[11];
+    // back-projection of the tied depth pixel (keyframe camera), into the view
+    float px, py, pz;
+    backproject_move(M, kfx, kfy, kcx, kcy, u, v, d, px, py, pz);
     float mx = 0.f, my = 0.f, qa = 0.f, qb = 0.f, qc = 0.f, R = 0.f;
     if (pz > ws.znear) {
       mx = vfx * (px / pz) + vcx;

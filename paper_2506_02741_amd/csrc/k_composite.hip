@@ -22,12 +22,19 @@
 //   last contributor for the backward.
 //
 // Backward replays the same list from the last contributor towards the
-// front, recovering T_i = T_{i+1} / (1 - alpha_i) and keeping the colour,
-// depth and coverage of everything behind i, B <- alpha x + (1 - alpha) B
-// with x = (c, z, 1).  Only g . B enters the gradient, so one scalar per
-// pixel is carried: S <- alpha (g . x) + (1 - alpha) S, S = g_C . bg at the
-// back.  Per contributing pair:
-//   dL/dalpha = T [g_C.(c - B_C) + g_D (z - B_D) + g_S (1 - B_S)] = T (g . x - S)
+// front, recovering T_i = T_{i+1} / (1 - alpha_i).  What lies behind
+// contributor i, normalised, is B_i = alpha_b x_b + (1 - alpha_b) B_b with
+// b the next contributor behind it and x = (c, z, 1), and B = (bg, 0, 0) at
+// the back; only g . (x_i - B_i) enters the gradient, carried per pixel by
+// the difference recurrence
+//   g.(x_i - B_i) = g.(x_i - x_b) + (1 - alpha_b) g.(x_b - B_b)
+// (x_b = (bg, 0, 0) and the second term 0 at the back).  Neighbouring
+// colours and depths are close, so their differences are exact or nearly,
+// and the result keeps its relative accuracy where x_i and B_i agree (a
+// surface seen through Gaussians of its own colour), which a running
+// g . B subtracted from g . x_i would lose to cancellation.  Per
+// contributing pair:
+//   dL/dalpha = T [g_C.(c - B_C) + g_D (z - B_D) + g_S (1 - B_S)] = T g.(x - B)
 //   dL/dc = alpha T g_C, dL/dz = alpha T g_D,
 //   if o G <= alpha_max: dL/do = G dL/dalpha, dL/dq = -o G dL/dalpha / 2
 // and q's dependence on the camera-frame centre p and the radius r
@@ -37,10 +44,11 @@
 //   k = 2 r^2 / p_z.
 // Mode "twist": dL/dp is chained straight to the view's left twist
 // (rho += dL/dp, phi += p x dL/dp) in registers, summed per tile.
-// Mode "slots": each lane adds its (dL/dc, dL/do, dL/dr) for an entry into
-// its wave's own LDS accumulators (LDS atomics, in the wave's program
-// order); after a batch the four waves' sums go to the pair's (record, tile)
-// slot, and a gather pass sums a record's slots.  Neither mode uses global
+// Mode "slots": each lane adds its (dL/dc, dL/do, dL/dr) -- and with
+// geometry its dL/dp -- for an entry into its wave's own LDS accumulators
+// (LDS atomics, in the wave's program order); after a batch the four waves'
+// sums go to the pair's (record, tile) slot, and a gather pass sums a
+// record's slots.  Neither mode uses global
 // atomics and no two waves share an accumulator, so both are deterministic.
 #include "vtgs_internal.h"
 
@@ -436,6 +444,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   constexpr int PER = (BATCH + NT - 1) / NT;
   constexpr int NCH = PER * NT / kWave;
   constexpr bool kTwist = (MODE & 1) != 0, kSlots = (MODE & 2) != 0;
+  constexpr bool kGeo = kSlots && (MODE & 4) != 0;  // slots also carry dL/dp
+  constexpr int NA = kGeo ? 8 : 5;                   // floats per slot
   constexpr int AB = kSlots ? BATCH : 1;
   constexpr int G = Group<TILE, BATCH>::G, NS = Group<TILE, BATCH>::NS, NR = NW * PPT;
   // staged entry: e0 (mx, my, qa, 2 qb), e1 (qc, o, z, qb), e2 (c, r)
@@ -443,7 +453,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   __shared__ float4 ejs[BATCH];   // (fx/z, fy/z, -fx px/z^2, -fy py/z^2)
   __shared__ float4 eps_[BATCH];  // (px, py, 2 r^2 / z, learnable)
   __shared__ uint32_t slot_s[AB];
-  __shared__ float acc[NW][5][AB];
+  __shared__ float acc[NW][NA][AB];
   __shared__ int maxlast_s;
   __shared__ float red_s[NW][7];
   __shared__ unsigned long long masks[NW][NCH];
@@ -460,9 +470,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   const int w = threadIdx.x / kWave;
 
   float px[PPT], py[PPT], T[PPT], gC0[PPT], gC1[PPT], gC2[PPT], gD[PPT], gS[PPT];
-  // g . B: the upstream gradient against what lies behind (colour, depth,
-  // coverage), one scalar per pixel
-  float SB[PPT];
+  // the difference recurrence: (1 - alpha_b) g.(x_b - B_b) of the
+  // contributor b behind (0 at the back), its colour and depth (the
+  // background and 0 at the back) and g_S (1 - its coverage x_S)
+  float E[PPT], XP0[PPT], XP1[PPT], XP2[PPT], XPZ[PPT], GS1[PPT];
   uint32_t last[PPT];
   uint32_t mylast = 0;
   float lsum = 0.f;  // this lane's share of the tile's Eq. 1 loss
@@ -503,7 +514,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       gD[k] = (valid && g_depth) ? g_depth[p] : 0.f;
       gS[k] = (valid && g_sil) ? g_sil[p] : 0.f;
     }
-    SB[k] = fmaf(gC0[k], ws.bg[0], fmaf(gC1[k], ws.bg[1], gC2[k] * ws.bg[2]));
+    E[k] = 0.f;
+    XP0[k] = ws.bg[0]; XP1[k] = ws.bg[1]; XP2[k] = ws.bg[2]; XPZ[k] = 0.f;
+    GS1[k] = gS[k];
     mylast = max(mylast, last[k]);
   }
   if (threadIdx.x == 0) maxlast_s = 0;
@@ -568,7 +581,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
 #pragma unroll
         for (int ww = 0; ww < NW; ww++)
 #pragma unroll
-          for (int c = 0; c < 5; c++) acc[ww][c][i] = 0.f;
+          for (int c = 0; c < NA; c++) acc[ww][c][i] = 0.f;
       }
     }
     __syncthreads();
@@ -653,22 +666,33 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const float Tk = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
           T[k] = Tk;
           const float wgt = ok ? a * Tk : 0.f;
-          // g . x for this Gaussian: x = (colour, depth, 1)
-          const float gx = fmaf(gC0[k], e2.x, fmaf(gC1[k], e2.y, fmaf(gC2[k], e2.z,
-                                                                  fmaf(gD[k], e1.z, gS[k]))));
-          const float dLda = ok ? (gx - SB[k]) * Tk : 0.f;
-          SB[k] = ok ? fmaf(a, gx, om * SB[k]) : SB[k];
+          // g . (x - B) for this Gaussian, x = (colour, depth, 1)
+          const float gdi =
+              fmaf(gC0[k], e2.x - XP0[k],
+                   fmaf(gC1[k], e2.y - XP1[k],
+                        fmaf(gC2[k], e2.z - XP2[k], fmaf(gD[k], e1.z - XPZ[k], GS1[k] + E[k]))));
+          const float dLda = ok ? gdi * Tk : 0.f;
+          E[k] = ok ? om * gdi : E[k];
+          XP0[k] = ok ? e2.x : XP0[k];
+          XP1[k] = ok ? e2.y : XP1[k];
+          XP2[k] = ok ? e2.z : XP2[k];
+          XPZ[k] = ok ? e1.z : XPZ[k];
+          GS1[k] = ok ? 0.f : GS1[k];
           const bool pass = oG <= amax;
           const float dLdq = pass ? -0.5f * oG * dLda : 0.f;
           const float qb = e1.w;
           const float w0 = fmaf(e0.z, dx, qb * dy), w1 = fmaf(qb, dx, e1.x * dy);
           const float t0 = ej.x * w0, t1 = ej.y * w1, t2 = fmaf(ej.z, w0, ej.w * w1);
-          if (kTwist) {
+          // dL/dp of this pair (camera-frame centre)
+          float g0v = 0.f, g1v = 0.f, g2v = 0.f;
+          if (kTwist || kGeo) {
             const float kk = ep.z;
-            const float g0v = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
-            const float g1v = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
+            g0v = dLdq * fmaf(kk * t0, t2, -2.0f * t0);
+            g1v = dLdq * fmaf(kk * t1, t2, -2.0f * t1);
             const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
-            const float g2v = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+            g2v = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
+          }
+          if (kTwist) {
             const float pz = e1.z;
             tw[0] += g0v; tw[1] += g1v; tw[2] += g2v;
             tw[3] += ep.y * g2v - pz * g1v;
@@ -683,6 +707,11 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
             atomicAdd(&acc[w][2][cur_i], wgt * gC2[k]);
             atomicAdd(&acc[w][3][cur_i], pass ? gau * dLda : 0.f);
             atomicAdd(&acc[w][4][cur_i], dLdq * (-2.0f * e2.w * tt));
+            if (kGeo) {
+              atomicAdd(&acc[w][5][cur_i], g0v);
+              atomicAdd(&acc[w][6][cur_i], g1v);
+              atomicAdd(&acc[w][7][cur_i], g2v);
+            }
           }
         }
       }
@@ -691,9 +720,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       __syncthreads();
       for (int i = threadIdx.x; i < nb; i += NT) {
         if (eps_[i].w == 0.f) continue;
-        float *o = ws.slots + 5 * (int64_t)slot_s[i];
+        float *o = ws.slots + NA * (int64_t)slot_s[i];
 #pragma unroll
-        for (int c = 0; c < 5; c++) {
+        for (int c = 0; c < NA; c++) {
           float s = 0.f;
 #pragma unroll
           for (int ww = 0; ww < NW; ww++) s += acc[ww][c][i];
@@ -709,9 +738,9 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       fetch_bwd_entry<true>(ws, n_rec, rec_base, ws.ids[i], E);
       const uint32_t sl = entry_slot(ws, E, tx, ty);
       if (sl == 0xffffffffu) continue;
-      float *o = ws.slots + 5 * (int64_t)sl;
+      float *o = ws.slots + NA * (int64_t)sl;
 #pragma unroll
-      for (int c = 0; c < 5; c++) o[c] = 0.f;
+      for (int c = 0; c < NA; c++) o[c] = 0.f;
     }
   }
   if (kTwist) {
@@ -748,6 +777,8 @@ hipError_t bwd_launch(const Ws &ws, const float *g_rgb, const float *g_depth, co
     case 1: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 1>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
     case 2: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 2>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
     case 3: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 3>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
+    case 6: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 6>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
+    case 7: hipLaunchKernelGGL((k_bwd<TILE, BATCH, 7>), g, b, 0, st, ws, g_rgb, g_depth, g_sil, tr); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -792,6 +823,7 @@ hipError_t launch_composite_bwd(const Ws &ws, const float *g_rgb, const float *g
                                 const vtgs_track_cfg *track) {
   if (ws.n_tiles == 0) return hipSuccess;
   TrackArgs tr{0.f, 0.f, 0.f, 0};
+  if (((mode & 4) != 0) != (ws.slot_w == 8) && (mode & 2)) return hipErrorInvalidValue;
   if (track) {
     if (mode != 1) return hipErrorInvalidValue;
     tr = TrackArgs{track->alpha, track->beta, track->sil_thr, 1};

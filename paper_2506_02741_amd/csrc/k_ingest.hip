@@ -1,6 +1,7 @@
 // Keyframe ingestion: a view-tied Gaussian at every valid depth pixel of the
 // stride grid (Sec. 3.2), radius initialised to stride * depth / focal
-// length (App. A).  Stream compaction in row-major order: per-block counts,
+// length (App. A); the complement mask of pixels the current Gaussians leave
+// uncovered (Sec. 3.4).  Stream compaction in row-major order: per-block counts,
 // a single-block scan of the block counts, then an order-preserving fill.
 #include "vtgs_internal.h"
 
@@ -90,7 +91,26 @@ inline void grid_dims(int H, int W, int s, int *nx, int64_t *M, int *nb) {
   *M = (int64_t)*nx * ny;
   *nb = (int)((*M + kCells - 1) / kCells);
 }
+
+// Complement initialisation (Sec. 3.4): a pixel is left uncovered by the
+// current Gaussians when the silhouette of their rendering there is below
+// thr, and gets a new Gaussian if its depth is valid.
+__global__ __launch_bounds__(kNT) void k_uncovered(const float *sil, const float *depth, int64_t n,
+                                                   float thr, uint8_t *mask) {
+  const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  const float d = depth[i];
+  mask[i] = (uint8_t)(sil[i] < thr && d > 0.f && d <= 3.402823466e38f);
+}
 }  // namespace
+
+hipError_t launch_uncovered(const float *sil, const float *depth, int64_t n, float thr,
+                            uint8_t *mask, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_uncovered, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, st, sil,
+                     depth, n, thr, mask);
+  return hipGetLastError();
+}
 
 int64_t ingest_scratch_words(int H, int W, int s) {
   int nx, nb;

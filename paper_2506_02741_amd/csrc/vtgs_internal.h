@@ -15,15 +15,18 @@ constexpr int kWave = 64;
 // Keyframe descriptor in device memory.
 struct DevKF {
   const uint32_t *pix;
-  const float *depth;
+  float *depth;
   float *color;      // [3][n]
   float *opacity;
   float *radius;
-  const float *pose; // [12]
+  float *pose;       // [12]
   float fx, fy, cx, cy;
   int32_t width, height, n, learnable;
   float *g_color, *g_opacity, *g_radius;
   float *adam;       // [10][n]
+  // geometry (learnable keyframes only): depth and pose gradients, Adam states
+  float *g_depth, *g_pose, *depth_adam, *pose_adam;
+  int32_t geo, pad;  // geo: the backward carries dLoss/d(centre) for it
 };
 
 // View descriptor: its records are [rec_base, rec_base + n_rec) and its
@@ -45,7 +48,9 @@ struct DevView {
 
 // One (view, keyframe) pair: records [rec_start, rec_start + n) are the
 // keyframe's Gaussians seen from the view.  M = view pose * keyframe pose^-1,
-// recomputed on the device before every preprocessing pass.
+// written by every preprocessing pass (by the thread of the segment's first
+// record) and read by the gradient gathers that turn dL/dp back into the
+// keyframe's frame.
 struct DevSeg {
   float M[12];
   int32_t view, kf, rec_start, n;
@@ -55,6 +60,7 @@ struct DevSeg {
 struct DevKFUse {
   int32_t rec_start;  // record index of the keyframe's Gaussian 0 in that view
   int32_t view;
+  int32_t seg;        // the (view, keyframe) segment
 };
 
 enum : uint32_t { kFlagCapacity = 1u, kFlagNonfinite = 2u };
@@ -94,7 +100,10 @@ struct Ws {
   unsigned long long *keys_tmp;// [cap]
   unsigned long long *lane_bits;// [(cap/64 + n_tiles + 2) * lane_bits_per_chunk(tile)]
   uint32_t *ids;               // [cap] sorted view-local ids
-  float *slots;                // [cap][5] per (record, tile) gradient partials
+  float *slots;                // [cap][slot_w] per (record, tile) gradient partials:
+                               // dL/dc (3), dL/do, dL/dr (, dL/dp in the view frame (3))
+  float *kpose_part;           // [n_kf][gblocks][8] keyframe pose twist partials
+  int32_t slot_w, gblocks;     // 5, or 8 with geometry; gather blocks per keyframe
   // per pixel
   float *t_final;              // [P]
   uint32_t *last;              // [P] contributors end (relative to tile start)
@@ -102,7 +111,7 @@ struct Ws {
   float *gimg;                 // [5][P] internal upstream gradients
   float *twist_part;           // [n_tiles][8]: six twist sums, the Eq. 1 loss, one unused
   float *loss_part;            // [n_views][loss_blocks][4]
-  float *ssim_map;             // [3 kinds][3 ch][P]
+  double *ssim_map;            // [3 kinds][3 ch][P], FP64
   float *ssim_part;            // [n_views][3][loss_blocks]
   int32_t loss_blocks, ssim_gx, ssim_gy, pad1;
   // render parameters
@@ -222,6 +231,8 @@ hipError_t launch_ingest_fill(const float *depth, const float *rgb, const uint8_
                               int n, uint32_t *pix, float *dep, float *col, float *opa,
                               float *rad, hipStream_t st);
 int64_t ingest_scratch_words(int H, int W, int s);
+hipError_t launch_uncovered(const float *sil, const float *depth, int64_t n, float thr,
+                            uint8_t *mask, hipStream_t st);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
@@ -232,15 +243,18 @@ hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st);
 hipError_t launch_scan_records(const Ws &ws, hipStream_t st);
 hipError_t launch_composite_fwd(const Ws &ws, float *rgb, float *depth, float *sil,
                                 hipStream_t st);
-// mode bit 0: twist partials per tile, bit 1: per-(record, tile) slots
-// mode 1: twist, 2: slots, 3: both.  track (mode 1 only, else NULL): the
+// mode bit 0: twist partials per tile, bit 1: per-(record, tile) slots,
+// bit 2 (with bit 1): the slots also carry dL/dp (the plan's slot_w is 8)
+// mode 1: twist, 2: slots, 3: both, 6 / 7: slots with geometry.  track (mode 1 only, else NULL): the
 // upstream gradient is Eq. 1's, evaluated per pixel from the internal images
 // and the views' observations (g_* ignored), and each tile's loss is kept.
 hipError_t launch_composite_bwd(const Ws &ws, const float *g_rgb, const float *g_depth,
                                 const float *g_sil, int mode, hipStream_t st,
                                 const vtgs_track_cfg *track = nullptr);
 hipError_t launch_twist_reduce(const Ws &ws, float *g_twist, hipStream_t st);
-// max_n: largest Gaussian count of a learnable keyframe
+// max_n: largest Gaussian count of a learnable keyframe.  Adds the slots'
+// sums (and the depth gradients) into the keyframes' gradient buffers and,
+// with geometry, the keyframe pose twists into g_pose.
 hipError_t launch_gather(const Ws &ws, int max_n, hipStream_t st);
 hipError_t launch_track_update(const Ws &ws, const vtgs_track_cfg &cfg, float *loss,
                                hipStream_t st);
@@ -248,6 +262,24 @@ hipError_t launch_map_loss(const Ws &ws, const vtgs_map_cfg &cfg, hipStream_t st
 hipError_t launch_map_update(const Ws &ws, const vtgs_map_cfg &cfg, int32_t *step, float *loss,
                              int max_n, hipStream_t st);
 int64_t rec_scan_blocks(int64_t n_rec);
+
+// visibility: targets of one launch, passed by value
+constexpr int kVisMaxTargets = 16;
+struct VisCam {
+  float fx, fy, cx, cy;
+  int32_t width, height;
+};
+struct VisTargets {
+  const float *depth[kVisMaxTargets];
+  const float *pose[kVisMaxTargets];
+  float fx[kVisMaxTargets], fy[kVisMaxTargets], cx[kVisMaxTargets], cy[kVisMaxTargets];
+  int32_t width[kVisMaxTargets], height[kVisMaxTargets];
+  int32_t n;
+};
+// first != 0: the mask is written, else OR-ed into; counts are added to
+hipError_t launch_visibility(const float *src_depth, const VisCam &sc, const float *src_pose,
+                             const VisTargets &tg, float tol, float znear, uint8_t *mask,
+                             int32_t *counts, int first, hipStream_t st);
 hipError_t launch_debug_copy(const Ws &ws, float *records, int32_t *rect, hipStream_t st);
 
 }  // namespace vtgs

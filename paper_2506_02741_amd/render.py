@@ -83,6 +83,9 @@ class Keyframe:
         self.learnable = bool(learnable)
         self.g_color = self.g_opacity = self.g_radius = None
         self.adam = None
+        # geometry: depth along the pixel rays and the keyframe pose
+        self.g_depth = self.g_pose = self.depth_adam = self.pose_adam = None
+        self.depth_map = None
 
     @classmethod
     def ingest(cls, depth_img, rgb_img, cam, pose, stride=1, o_init=0.99, mask=None,
@@ -111,7 +114,9 @@ class Keyframe:
         check(L.vtgs_ingest_fill(_ptr(d), _ptr(rgb), _ptr(m), H, W, stride, float(cam.fx),
                                  float(o_init), _ptr(scratch), nbytes, n, _ptr(pix), _ptr(dep),
                                  _ptr(col), _ptr(opa), _ptr(rad), st))
-        return cls(cam, pose, pix, dep, col, opa, rad, learnable, dev)
+        k = cls(cam, pose, pix, dep, col, opa, rad, learnable, dev)
+        k.depth_map = d.reshape(-1)  # the frame's depth map (visibility tests)
+        return k
 
     def with_grad_buffers(self):
         dev = self.depth.device
@@ -124,12 +129,29 @@ class Keyframe:
         self.adam = torch.zeros(10, self.n, device=self.depth.device)
         return self
 
+    def with_geometry_grads(self):
+        """Gradient buffers of the tied depths [n] and the pose twist [6]
+        (render_bwd adds into them; a learnable keyframe only)."""
+        dev = self.depth.device
+        self.g_depth = torch.zeros(self.n, device=dev)
+        self.g_pose = torch.zeros(6, device=dev)
+        return self
+
+    def with_geometry_adam(self, depth=True, pose=True):
+        """Adam states that let map_step move the Gaussians along their rays
+        (depth) and adjust the keyframe pose (bundle adjustment)."""
+        dev = self.depth.device
+        self.depth_adam = torch.zeros(2, self.n, device=dev) if depth else None
+        self.pose_adam = torch.zeros(13, device=dev) if pose else None
+        return self
+
     def cstruct(self):
         return _lib.vtgs_keyframe(self.n, _ptr(self.pix), _ptr(self.depth), _ptr(self.color),
                                   _ptr(self.opacity), _ptr(self.radius), _ptr(self.pose),
                                   self.cam.cstruct(), 1 if self.learnable else 0,
                                   _ptr(self.g_color), _ptr(self.g_opacity), _ptr(self.g_radius),
-                                  _ptr(self.adam))
+                                  _ptr(self.adam), _ptr(self.g_depth), _ptr(self.g_pose),
+                                  _ptr(self.depth_adam), _ptr(self.pose_adam))
 
 
 class View:
@@ -170,8 +192,14 @@ def track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002, sil_thr=0.5):
     return _lib.vtgs_track_cfg(alpha, beta, lr_rot, lr_trans, sil_thr)
 
 
-def map_cfg(rho=0.8, tau=0.2, sigma=1.0, lr_color=0.0025, lr_opacity=0.05, lr_radius=0.005):
-    return _lib.vtgs_map_cfg(rho, tau, sigma, lr_color, lr_opacity, lr_radius)
+def map_cfg(rho=0.8, tau=0.2, sigma=1.0, lr_color=0.0025, lr_opacity=0.05, lr_radius=0.005,
+            lr_depth=0.001, lr_trans=0.002, lr_rot=0.002):
+    """Eq. 2 weights and App. A's learning rates; lr_depth (tied depths of
+    movable keyframes) and lr_trans / lr_rot (poses under bundle adjustment)
+    are readings (the paper gives none for them: the pose rates are its
+    tracking rates)."""
+    return _lib.vtgs_map_cfg(rho, tau, sigma, lr_color, lr_opacity, lr_radius, lr_depth,
+                             lr_trans, lr_rot)
 
 
 def keyframe_array(keyframes):
@@ -207,11 +235,11 @@ class Plan:
         self.n_tiles = int(self.L.vtgs_plan_tiles(h))
         self.cap = int(self.L.vtgs_plan_pair_capacity(h))
         self.offsets = [int(self.L.vtgs_plan_view_offset(h, v)) for v in range(len(self.views))]
+        self.generation = 0
         if workspace is not None and workspace.numel() >= self.ws_bytes:
             self.ws = workspace
         else:
             self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        self.generation = 0
         if bind:
             self.bind(stream)
 

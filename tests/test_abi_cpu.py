@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_version_and_defaults(L):
     from paper_2506_02741_amd import _lib
-    assert L.vtgs_abi_version() == 1
+    assert L.vtgs_abi_version() == _lib.VTGS_ABI_VERSION == 2
     p = _lib.default_params()
     assert p.tile == 16 and p.batch == 256
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.alpha_max - 0.99) < 1e-7

@@ -1,0 +1,161 @@
+"""Geometry gradients through the C ABI against the oracle: each Gaussian's
+tied depth (the supplementary's Gaussians movable along their pixel rays)
+and each keyframe's pose twist through its Gaussians' centres (Sec. 3.5,
+bundle adjustment), from render_bwd and inside map_step.
+
+Bars as in the other parity tests: per element
+|g - g_ref| <= 1e-3 max(|g_ref|, 1e-4 max|g_ref|), upstream gradients zeroed
+at flagged pixels; Adam steps against an FP64 Adam from the GPU's own
+gradient and state."""
+import numpy as np
+import pytest
+
+from scenes import oracle_kf, room_frames
+from test_gpu_parity import MARGIN, T, grad_close, np_
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    torch.cuda.set_device(0)
+    from paper_2506_02741_amd import render
+    return render
+
+
+def _section(R, seed, w, h, n_kf, geo=(True, True)):
+    cam, frames, vpose = room_frames(seed, w, h, n_kf=n_kf)
+    ks = []
+    for i, f in enumerate(frames):
+        k = R.Keyframe.ingest(f.depth, f.rgb, cam.as_tuple(), f.pose, 1, 0.99, None, True)
+        k.with_grad_buffers()
+        if geo[i % len(geo)]:
+            k.with_geometry_grads()
+        ks.append(k)
+    return cam, frames, vpose, ks
+
+
+@pytest.mark.parametrize("tile,batch", [(16, 256), (8, 128), (32, 512)])
+def test_depth_and_pose_gradients(R, orc, tile, batch):
+    """Two keyframes rendered from a view 3 cm / 2 degrees off the first:
+    colour/opacity/radius (now through 8-float slots), the tied-depth
+    gradient of every Gaussian and both keyframes' pose twists."""
+    cam, frames, vpose, ks = _section(R, 9, 80, 60, 2)
+    plan = R.Plan(ks, [R.View(cam.as_tuple(), vpose, 0, 2)], R.params(tile=tile, batch=batch))
+    plan.render_fwd()
+    assert plan.status()[0] == 0
+    okfs = [oracle_kf(orc, f) for f in frames]
+    ov = orc.ViewSpec(cam.as_tuple(), vpose, 0, 2)
+    ref = orc.render(ov, okfs, margin=MARGIN)
+    rng = np.random.default_rng(31)
+    P = plan.P
+    g_rgb = rng.normal(size=(3, P)); g_d = rng.normal(size=P); g_s = rng.normal(size=P)
+    m = ref["marginal"]
+    g_rgb[:, m] = 0; g_d[m] = 0; g_s[m] = 0
+    tw = np_(plan.render_bwd(T(g_rgb), T(g_d), T(g_s)))
+    gref = orc.render_bwd(ov, okfs, g_rgb, g_d, g_s)
+    got = dict(color=np.concatenate([np_(k.g_color) for k in ks], 1),
+               opacity=np.concatenate([np_(k.g_opacity) for k in ks]),
+               radius=np.concatenate([np_(k.g_radius) for k in ks]),
+               depth=np.concatenate([np_(k.g_depth) for k in ks]))
+    for name in ("color", "opacity", "radius", "depth"):
+        ok, worst = grad_close(got[name], gref[name], name, gref["mag"][name])
+        assert ok, (name, worst)
+    for i, k in enumerate(ks):
+        ok, worst = grad_close(np_(k.g_pose), gref["kf_pose"][i], "pose of keyframe %d" % i,
+                               gref["mag"]["kf_pose"][i])
+        assert ok, (i, worst, np_(k.g_pose), gref["kf_pose"][i])
+    ok, worst = grad_close(tw[0], gref["twist"], "view twist", gref["mag"]["twist"])
+    assert ok, worst
+
+
+def test_geometry_buffers_of_one_keyframe_only(R, orc):
+    """Only the first keyframe asks for geometry: its depth and pose
+    gradients match the oracle and the second's colour gradients are
+    unchanged by the wider slots (bitwise equal to a plan without geometry)."""
+    cam, frames, vpose, ks = _section(R, 11, 64, 48, 2, geo=(True, False))
+    view = R.View(cam.as_tuple(), vpose, 0, 2)
+    rng = np.random.default_rng(5)
+    plan = R.Plan(ks, [view])
+    plan.render_fwd()
+    g_rgb = T(rng.normal(size=(3, plan.P)))
+    plan.render_bwd(g_rgb, None, None, twist=False)
+    c1 = np_(ks[1].g_color).copy()
+    plain = [R.Keyframe(cam.as_tuple(), f.pose, k.pix, k.depth, k.color, k.opacity, k.radius,
+                        learnable=True).with_grad_buffers() for f, k in zip(frames, ks)]
+    p2 = R.Plan(plain, [view])
+    p2.render_fwd()
+    p2.render_bwd(g_rgb, None, None, twist=False)
+    assert np.array_equal(np_(plain[1].g_color), c1)
+    assert np.array_equal(np_(plain[0].g_color), np_(ks[0].g_color))
+    okfs = [oracle_kf(orc, f) for f in frames]
+    ov = orc.ViewSpec(cam.as_tuple(), vpose, 0, 2)
+    assert not orc.render(ov, okfs, margin=MARGIN)["marginal"].any()
+    gref = orc.render_bwd(ov, okfs, np_(g_rgb).astype(np.float64), None, None)
+    ok, worst = grad_close(np_(ks[0].g_depth), gref["depth"][:ks[0].n], "depth",
+                           gref["mag"]["depth"][:ks[0].n])
+    assert ok, worst
+    ok, worst = grad_close(np_(ks[0].g_pose), gref["kf_pose"][0], "pose", gref["mag"]["kf_pose"][0])
+    assert ok, worst
+
+
+def test_map_step_moves_depths_and_pose(R, orc):
+    """map_step with depth and pose Adam states (one keyframe of two): after
+    one step the depths and the pose are the FP64 Adam step (lr_depth, and
+    lr_trans / lr_rot on the twist followed by the retraction) from the
+    gradients the step used, which match the oracle's backward of the step's
+    own upstream images."""
+    import torch
+    # (view poses chosen so that no pixel holds a near-tie decision: the
+    # step's own upstream images cannot be zeroed there)
+    cam, frames, vpose, ks = _section(R, 11, 64, 48, 2, geo=(True, False))
+    for k in ks:
+        k.with_adam()
+    ks[0].with_geometry_adam()
+    obs = [frames[0], frames[0]]
+    poses = [frames[0].pose, vpose]
+    views = [R.View(cam.as_tuple(), p, 0, 2, f.rgb, f.depth) for p, f in zip(poses, obs)]
+    plan = R.Plan(ks, views)
+    d0 = np_(ks[0].depth).astype(np.float64).copy()
+    pose0 = np_(ks[0].pose).astype(np.float64).reshape(3, 4).copy()
+    okfs = [oracle_kf(orc, f) for f in frames]
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cfg = R.map_cfg(lr_depth=0.001, lr_trans=0.002, lr_rot=0.002)
+    plan.map_step(step, cfg)
+    img, gimg = (np_(x).astype(np.float64) for x in plan.debug_images())
+    for k in ks:
+        k.g_color.zero_()
+    ks[0].g_depth.zero_(); ks[0].g_pose.zero_()
+    plan.debug_gather()
+    assert plan.status()[0] == 0
+    P = 64 * 48
+    gd = np.zeros(ks[0].n); gp = np.zeros(6); md = np.zeros(ks[0].n); mp = np.zeros(6)
+    for v, pv in enumerate(poses):
+        ov = orc.ViewSpec(cam.as_tuple(), pv, 0, 2)
+        assert not orc.render(ov, okfs, margin=MARGIN)["marginal"].any()
+        sl = slice(v * P, (v + 1) * P)
+        g = orc.render_bwd(ov, okfs, gimg[:3, sl], gimg[3, sl], None)
+        gd += g["depth"][:ks[0].n]; gp += g["kf_pose"][0]
+        md += g["mag"]["depth"][:ks[0].n]; mp += g["mag"]["kf_pose"][0]
+    got_d = np_(ks[0].g_depth).astype(np.float64); got_p = np_(ks[0].g_pose).astype(np.float64)
+    ok, worst = grad_close(got_d, gd, "map depth", md); assert ok, worst
+    ok, worst = grad_close(got_p, gp, "map pose", mp); assert ok, worst
+    # FP64 Adam from the GPU's gradients: first step -lr g / (|g| + eps)
+    dm = np.zeros_like(d0); dv = np.zeros_like(d0); x = d0.copy()
+    orc.adam(x, got_d, dm, dv, 1, 0.001)
+    assert np.allclose(np_(ks[0].depth), x, rtol=0, atol=2e-6)
+    ad = np_(ks[0].depth_adam).astype(np.float64)
+    assert np.allclose(ad[0], dm, rtol=2e-6, atol=1e-12)
+    xi = np.zeros(6); pm = np.zeros(6); pv = np.zeros(6)
+    for c in range(6):
+        xc, mc, vc = xi[c:c + 1].copy(), pm[c:c + 1], pv[c:c + 1]
+        orc.adam(xc, got_p[c:c + 1], mc, vc, 1, 0.002)
+        xi[c] = xc[0]
+    pose_ref = orc.compose(orc.se3_exp(xi), pose0)
+    assert np.allclose(np_(ks[0].pose).astype(np.float64).reshape(3, 4), pose_ref, atol=2e-6)
+    assert float(np_(ks[0].pose_adam)[12]) == 1.0
+    # the second keyframe keeps its depths and pose
+    assert np.array_equal(np_(ks[1].depth), frames[1].depth.ravel())
+    assert np.array_equal(np_(ks[1].pose), frames[1].pose.ravel())

@@ -295,3 +295,150 @@ def test_stage_timing_with_repeats_changes_nothing(R):
     assert stages["preprocess"][1] == 1, stages
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
+
+
+# ----------------------------------------------------------------------------
+# map_step and track_step in magnitude, two optimiser steps each
+# ----------------------------------------------------------------------------
+
+def _near_flagged(orc, ov, okfs, flagged_px, W):
+    """Local ids of the Gaussians whose extent box (mu +- R, one pixel wider)
+    holds a flagged pixel: their gradients may follow either outcome."""
+    rec = orc.preprocess32(ov, okfs)
+    near = np.zeros(rec.shape[0], bool)
+    for p in flagged_px:
+        x, y = p % W, p // W
+        near |= (rec["count"] > 0) & (np.abs(rec["mx"] - x) <= rec["ext"] + 1) & \
+            (np.abs(rec["my"] - y) <= rec["ext"] + 1)
+    return near
+
+
+def _map_state(k):
+    n = k.n
+    ad = np_(k.adam).astype(np.float64)
+    return dict(color=np_(k.color).astype(np.float64), opacity=np_(k.opacity).astype(np.float64),
+                radius=np_(k.radius).astype(np.float64), m=ad[:5], v=ad[5:])
+
+
+def test_map_step_gradients_and_adam_two_steps(R, orc):
+    """Two map_step iterations over a two-keyframe section seen by two views
+    (Sec. 3.4, Eq. 2; App. A learning rates), each checked stage by stage
+    against the oracle from the GPU's own state at that step:
+    - the rendered images (1e-5, every pixel, near-ties by their outcomes);
+    - the upstream gradient images Eq. 2 forms from them (L1 and SSIM terms)
+      and the per-view loss, against the oracle's Eq. 2 on the same images;
+    - the per-Gaussian gradients the Adam step used (slots summed over both
+      views), against the oracle's backward of those upstream images summed
+      over views, at the 1e-3 relative bar;
+    - the Adam moments and the new (c, o, r) against an FP64 Adam step on
+      (c, logit o, log r) from the GPU's gradient and previous state."""
+    import torch
+    from test_gpu_parity import check_images, grad_close, oracle_ref
+    cam, frames, _ = room_frames(9, 64, 48, n_kf=2)
+    c = cam.as_tuple()
+    W, H = c[4], c[5]
+    P = W * H
+    inp = _section_inputs(frames)
+    ks = [R.Keyframe(c, f.pose, d["pix"].astype(np.int32), d["depth"], d["color"], d["opacity"],
+                     d["radius"], learnable=True).with_adam().with_grad_buffers()
+          for f, d in zip(frames, inp)]
+    views = [R.View(c, f.pose, 0, 2, f.rgb, f.depth) for f in frames]
+    plan = R.Plan(ks, views)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cfg = dict(rho=0.8, tau=0.2, sigma=1.0)
+    lrs = [0.0025, 0.0025, 0.0025, 0.05, 0.005]
+    n0 = ks[0].n
+    before = [_map_state(k) for k in ks]
+    for t in (1, 2):
+        okfs = [orc.Keyframe(c, f.pose, d["pix"], d["depth"], s["color"].astype(np.float32),
+                             s["opacity"].astype(np.float32), s["radius"].astype(np.float32))
+                for f, d, s in zip(frames, inp, before)]
+        for k in ks:
+            k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+        loss = np_(plan.map_step(step, R.map_cfg(**cfg)))
+        img, gimg = (np_(x).astype(np.float64) for x in plan.debug_images())
+        plan.debug_gather()
+        assert plan.status()[0] == 0 and int(step.item()) == t
+        gc = np.zeros((3, sum(k.n for k in ks))); go = np.zeros(gc.shape[1]); gr = np.zeros(gc.shape[1])
+        mc = np.zeros_like(gc); mo = np.zeros_like(go); mr = np.zeros_like(gr)
+        skip = np.zeros(gc.shape[1], bool)
+        for v, f in enumerate(frames):
+            sl = slice(v * P, (v + 1) * P)
+            ov = orc.ViewSpec(c, f.pose, 0, 2)
+            ref = oracle_ref(orc, ov, okfs)
+            check_images(img[:3, sl], img[3, sl], img[4, sl], ref)
+            # Eq. 2 on the GPU's own images: the upstream gradients exactly
+            L, g_rgb, g_d = orc.map_loss(H, W, img[:3, sl], img[3, sl], f.rgb, f.depth,
+                                         cfg["rho"], cfg["tau"], cfg["sigma"])
+            assert abs(loss[v] - L) <= 1e-5 * abs(L), (t, v, loss[v], L)
+            ok, worst = grad_close(gimg[:3, sl], g_rgb, "d Eq.2 / d rgb (t=%d)" % t)
+            assert ok, worst
+            ok, worst = grad_close(gimg[3, sl], g_d, "d Eq.2 / d depth (t=%d)" % t)
+            assert ok, worst
+            assert not gimg[4, sl].any()
+            g = orc.render_bwd(ov, okfs, gimg[:3, sl], gimg[3, sl], None)
+            gc += g["color"]; go += g["opacity"]; gr += g["radius"]
+            mc += g["mag"]["color"]; mo += g["mag"]["opacity"]; mr += g["mag"]["radius"]
+            skip |= _near_flagged(orc, ov, okfs, np.nonzero(ref["marginal"])[0], W)
+        got = [np.concatenate([np_(k.g_color) for k in ks], 1), np.concatenate([np_(k.g_opacity) for k in ks]),
+               np.concatenate([np_(k.g_radius) for k in ks])]
+        assert skip.mean() < 0.05
+        for a, b, m, name in zip(got, (gc, go, gr), (mc, mo, mr), ("colour", "opacity", "radius")):
+            ok, worst = grad_close(a[..., ~skip], b[..., ~skip], "map %s (t=%d)" % (name, t),
+                                   m[..., ~skip])
+            assert ok, worst
+        # Adam on (c, logit o, log r) in FP64 from the GPU's gradient and state
+        after = [_map_state(k) for k in ks]
+        for i, (k, b0, a1) in enumerate(zip(ks, before, after)):
+            sl = slice(0, n0) if i == 0 else slice(n0, n0 + k.n)
+            o0, r0 = b0["opacity"], b0["radius"]
+            x = np.concatenate([b0["color"], np.log(o0 / (1 - o0))[None], np.log(r0)[None]], 0)
+            gx = np.concatenate([got[0][:, sl], (got[1][sl] * o0 * (1 - o0))[None],
+                                 (got[2][sl] * r0)[None]], 0).astype(np.float64)
+            m, vv = b0["m"].copy(), b0["v"].copy()
+            for ch in range(5):
+                xc, mc, vc = x[ch].copy(), m[ch].copy(), vv[ch].copy()
+                orc.adam(xc, gx[ch], mc, vc, t, lrs[ch])
+                x[ch], m[ch], vv[ch] = xc, mc, vc
+            assert np.allclose(a1["m"], m, rtol=2e-6, atol=1e-12), (t, i)
+            assert np.allclose(a1["v"], vv, rtol=5e-6, atol=1e-18), (t, i)
+            assert np.allclose(a1["color"], x[:3], rtol=0, atol=2e-6)
+            assert np.allclose(a1["opacity"], 1 / (1 + np.exp(-x[3])), rtol=2e-6, atol=0)
+            assert np.allclose(a1["radius"], np.exp(x[4]), rtol=2e-6, atol=0)
+        before = after
+
+
+def test_track_two_iterations(R, orc):
+    """Two tracking iterations (Sec. 3.3, Eq. 1; Adam on the twist with App.
+    A's rates, then the retraction): the second starts from the GPU's pose
+    and moments after the first, and its loss, gradient-driven moments and
+    new pose match the oracle's iteration from that state."""
+    from paper_2506_02741_amd import synth
+    w = synth.tracking_workload(1, 160, 120)
+    kf = w["keyframe"]
+    cam = kf.cam.as_tuple()
+    k = R.Keyframe.ingest(kf.depth, kf.rgb, cam, kf.pose)
+    view = R.View(cam, w["init_pose"], obs_rgb=kf.rgb, obs_depth=kf.depth).with_pose_adam()
+    plan = R.Plan([k], [view])
+    cfg = R.track_cfg(alpha=0.5, beta=1.0, lr_rot=0.002, lr_trans=0.002)
+    okfs = [oracle_kf(orc, kf)]
+    pose = np.asarray(w["init_pose"], np.float32)
+    state = dict(m=np.zeros(6), v=np.zeros(6), t=0)
+    for t in (1, 2):
+        loss = np_(plan.track_step(cfg, iters=1))[0, 0]
+        assert plan.status()[0] == 0
+        L_ref, pose_ref, st, g_ref, _ = orc.track_iteration(orc.ViewSpec(cam, pose), okfs, kf.rgb,
+                                                            kf.depth, state)
+        assert abs(loss - L_ref) <= 1e-5 * abs(L_ref), (t, loss, L_ref)
+        ad = np_(view.pose_adam).astype(np.float64)
+        assert ad[12] == t
+        gmax = np.abs(g_ref).max()
+        # m = b1 m + (1 - b1) g: the gradient's 1e-3 bar scaled by (1 - b1)
+        assert np.all(np.abs(ad[:6] - st["m"]) <= 1e-4 * np.maximum(np.abs(g_ref), 1e-4 * gmax) + 1e-7 * np.abs(st["m"])), (t, ad[:6], st["m"])
+        # v = b2 v + (1 - b2) g^2: twice the gradient's relative bar on the new term
+        assert np.allclose(ad[6:12], st["v"], rtol=2e-3, atol=0), (t, ad[6:12], st["v"])
+        newp = np_(view.pose).astype(np.float64).reshape(3, 4)
+        assert np.allclose(newp, pose_ref, atol=4e-6), (t, newp, pose_ref)
+        # the next iteration starts from the GPU's state
+        pose = np_(view.pose).reshape(3, 4).copy()
+        state = dict(m=ad[:6].copy(), v=ad[6:12].copy(), t=t)

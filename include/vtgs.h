@@ -30,9 +30,10 @@
  *  - Pixel (u, v) = (column, row); centres at integer coordinates; images
  *    are row-major; RGB is planar [3][P].
  *  - Every pointer documented "device" is HIP device memory owned by the
- *    caller.  The library allocates no device memory: all its state lives in
- *    a caller-owned workspace sized by vtgs_plan_workspace_bytes().  It keeps
- *    host-side plan objects only.
+ *    caller.  The library allocates no device memory: a plan's state lives in
+ *    a caller-owned workspace sized by vtgs_plan_workspace_bytes(), or in the
+ *    library's static scratch (vtgs_render_fwd_static).  It keeps host-side
+ *    plan objects only.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
  *    compute calls are asynchronous on that stream and never synchronise,
  *    except vtgs_plan_status().
@@ -210,6 +211,26 @@ int vtgs_plan_status(vtgs_plan *plan, int64_t *pairs_needed, int32_t clear, void
  * per-pixel state the backward needs (final transmittance, last
  * contributor) stays in the workspace. */
 int vtgs_render_fwd(vtgs_plan *plan, float *rgb, float *depth, float *sil, void *stream);
+
+/* ---- render_fwd_static: render_fwd for callers that cannot allocate ------
+ * For callers that cannot allocate device memory or be handed a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same forward as vtgs_render_fwd, with the plan's state
+ * kept in the library's own static scratch of VTGS_STATIC_SCRATCH_BYTES on
+ * the current device instead of a caller workspace.  The plan need not be
+ * bound; afterwards it is bound to that scratch (render_bwd, track_step and
+ * map_step then use it too) until vtgs_plan_bind rebinds it.  A plan whose
+ * vtgs_plan_workspace_bytes exceeds the scratch is VTGS_E_WORKSPACE, with
+ * nothing enqueued.  The call allocates no device memory.  The first call
+ * with a plan on a device (or after another plan used the device's
+ * scratch) uploads the plan's descriptor tables with an asynchronous
+ * host-to-device copy from host memory the plan owns and clears the
+ * scratch's counters with fill kernels; later calls with the same plan only
+ * enqueue kernels.  Every plan on a device shares that device's scratch, so
+ * calls that overlap on one device -- on different streams, or a plan's
+ * state read after another plan used the scratch -- race. */
+#define VTGS_STATIC_SCRATCH_BYTES (128ll << 20)
+int vtgs_render_fwd_static(vtgs_plan *plan, float *rgb, float *depth, float *sil, void *stream);
 
 /* ---- render_bwd: gradients of a scalar loss through the last render_fwd --
  * g_rgb [3][P], g_depth [P], g_sil [P]: dLoss/d(outputs), device, NULL = 0.

@@ -20,6 +20,7 @@ VTGS_E_WORKSPACE = -3
 VTGS_E_CAPACITY = -4
 VTGS_E_NONFINITE = -5
 VTGS_N_STAGES = 10
+VTGS_STATIC_SCRATCH_BYTES = 128 << 20
 
 
 class vtgs_camera(C.Structure):
@@ -89,6 +90,7 @@ SIGNATURES = {
     "vtgs_plan_bind": (C.c_int, [_P, _P, _I64, _P]),
     "vtgs_plan_status": (C.c_int, [_P, _P, _I32, _P]),
     "vtgs_render_fwd": (C.c_int, [_P, _P, _P, _P, _P]),
+    "vtgs_render_fwd_static": (C.c_int, [_P, _P, _P, _P, _P]),
     "vtgs_render_bwd": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "vtgs_track_step": (C.c_int, [_P, _P, _I32, _P, _P]),
     "vtgs_map_step": (C.c_int, [_P, _P, _P, _P, _P]),

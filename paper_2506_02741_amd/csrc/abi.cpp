@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -55,6 +56,22 @@ void pinned_give(void *p, size_t cap) {
   (void)hipHostFree(p);
 }
 
+// The library's own scratch for vtgs_render_fwd_static: one copy per GPU
+// (each device that loads the library holds it until the process ends).
+// Host code never passes `g_scratch` itself to a kernel or a copy (in host
+// code the name is a host-side stand-in, not a device address): it uses the
+// address hipGetSymbolAddress gives for the current device.
+static __device__ __align__(256) char g_scratch[VTGS_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxStaticDevices = 64;
+struct StaticSlot {
+  char *ptr = nullptr;  // device address of g_scratch on this device
+  uint64_t owner = 0;   // id of the plan whose descriptors it holds (0: none)
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxStaticDevices];
+std::atomic<uint64_t> g_plan_ids{0};
+
 int fail(int code, const std::string &msg) {
   g_err = msg;
   return code;
@@ -76,6 +93,7 @@ struct Region {
 }  // namespace
 
 struct vtgs_plan {
+  uint64_t id = 0;  // unique per plan (owner tag of the static scratch)
   std::vector<DevKF> kfs;
   std::vector<DevView> views;
   std::vector<DevSeg> segs;
@@ -546,6 +564,7 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
     p->cap = cap;
     layout(p);
     desc_image(p);
+    p->id = ++g_plan_ids;
     *out = p;
     return VTGS_OK;
   } catch (...) {
@@ -555,6 +574,11 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
 
 void vtgs_plan_destroy(vtgs_plan *p) {
   if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    for (StaticSlot &s : g_static)
+      if (s.owner == p->id) s.owner = 0;
+  }
   if (p->upload_done) {
     (void)hipEventSynchronize(p->upload_done);
     (void)hipEventDestroy(p->upload_done);
@@ -637,6 +661,39 @@ int vtgs_render_fwd(vtgs_plan *p, float *rgb, float *depth, float *sil, void *st
     return run_forward(p, rgb, depth, sil, (hipStream_t)stream);
   } catch (...) {
     return fail(VTGS_E_HIP, "render_fwd: unexpected exception");
+  }
+}
+
+int vtgs_render_fwd_static(vtgs_plan *p, float *rgb, float *depth, float *sil, void *stream) {
+  try {
+    if (!p) return fail(VTGS_E_ARG, "render_fwd_static: plan is NULL");
+    if (p->ws_bytes > (int64_t)VTGS_STATIC_SCRATCH_BYTES)
+      return fail(VTGS_E_WORKSPACE, "render_fwd_static: the plan needs " +
+                                        std::to_string(p->ws_bytes) + " bytes, the static scratch holds " +
+                                        std::to_string((int64_t)VTGS_STATIC_SCRATCH_BYTES));
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxStaticDevices)
+      return fail(VTGS_E_ARG, "render_fwd_static: device index beyond " + std::to_string(kMaxStaticDevices));
+    hipStream_t st = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    StaticSlot &slot = g_static[dev];
+    if (!slot.ptr) {
+      // this device's copy of the array, with the device current
+      void *ptr = nullptr;
+      HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_scratch)));
+      if (!ptr || reinterpret_cast<uintptr_t>(ptr) % kAlign)
+        return fail(VTGS_E_HIP, "render_fwd_static: static scratch address unusable");
+      slot.ptr = (char *)ptr;
+    }
+    if (slot.owner != p->id || p->ws != slot.ptr) {
+      slot.owner = 0;
+      if (int rc = bind_to(p, slot.ptr, p->desc_host.data(), st)) return rc;
+      slot.owner = p->id;
+    }
+    return run_forward(p, rgb, depth, sil, st);
+  } catch (...) {
+    return fail(VTGS_E_HIP, "render_fwd_static: unexpected exception");
   }
 }
 

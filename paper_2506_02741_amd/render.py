@@ -236,6 +236,10 @@ class Plan:
         self.cap = int(self.L.vtgs_plan_pair_capacity(h))
         self.offsets = [int(self.L.vtgs_plan_view_offset(h, v)) for v in range(len(self.views))]
         self.generation = 0
+        if isinstance(workspace, str) and workspace == "static":
+            # state in the library's static scratch (render_fwd_static binds it)
+            self.ws = None
+            return
         if workspace is not None and workspace.numel() >= self.ws_bytes:
             self.ws = workspace
         else:
@@ -271,6 +275,14 @@ class Plan:
         if rgb is None and depth is None and sil is None:
             rgb, depth, sil = self.empty_images()
         check(self.L.vtgs_render_fwd(self.h, _ptr(rgb), _ptr(depth), _ptr(sil), _stream(stream)))
+        self.generation += 1
+        return rgb, depth, sil
+
+    def render_fwd_static(self, rgb, depth, sil, stream=None):
+        """render_fwd with the plan's state in the library's static scratch
+        (no device allocation by the library; the caller passes the outputs)."""
+        check(self.L.vtgs_render_fwd_static(self.h, _ptr(rgb), _ptr(depth), _ptr(sil),
+                                            _stream(stream)))
         self.generation += 1
         return rgb, depth, sil
 

@@ -36,6 +36,9 @@ sys.path.insert(0, ROOT)
 
 
 
+args = None  # the command line, set by main()
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -537,23 +540,55 @@ def serving_run(seconds, rate, n_sections, budget_gib, seed=4, low_rate=0.0):
         return rgb, depth
     budget = int(budget_gib * (1 << 30))
 
-    def run(r, sd, warm_first):
+    def run(r, sd, warm_first, secs=seconds, pipeline=True):
         """One server on a fresh allocator state; freed before returning."""
         if warm_first:   # kernels and allocator warmed on a short prefix
-            w = serve.Server(kfs, sections, budget_bytes=budget, max_active=64)
+            w = serve.Server(kfs, sections, budget_bytes=budget, max_active=64, pipeline=pipeline)
             w.run_trace(serve.poisson_trace(np.random.default_rng(seed + 2), r, 0.3, n_sections,
                                             cams, poses_for, obs_for), realtime=False)
             del w
-        srv = serve.Server(kfs, sections, budget_bytes=budget, max_active=64)
-        out = srv.run_trace(serve.poisson_trace(np.random.default_rng(sd), r, seconds, n_sections,
+        srv = serve.Server(kfs, sections, budget_bytes=budget, max_active=64, pipeline=pipeline)
+        out = srv.run_trace(serve.poisson_trace(np.random.default_rng(sd), r, secs, n_sections,
                                                 cams, poses_for, obs_for), realtime=True)
         out["peak_admitted_gib"] = srv.peak_mem / (1 << 30)
         del srv
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         return out
+
+    def drain(n_req, batched):
+        """The same n_req requests, all queued at once: served in batched,
+        pipelined ticks, or one request per launch (a single active request,
+        each tick waited for)."""
+        trace = serve.poisson_trace(np.random.default_rng(seed + 7), 1000.0, n_req / 1000.0,
+                                    n_sections, cams, poses_for, obs_for)
+        srv = serve.Server(kfs, sections, budget_bytes=budget, max_active=64 if batched else 1,
+                           pipeline=batched)
+        out = srv.run_trace(trace, realtime=False)
+        del srv
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out
+
+    # served form against one request per launch, on the same requests
+    drain(20, True); drain(5, False)   # warm both paths
+    d_b, d_1 = drain(args.serve_drain, True), drain(args.serve_drain, False)
+    served = dict(requests=d_b["requests"], batched_req_per_s=d_b["req_per_s"],
+                  batched_mpix_per_s=d_b["mpix_per_s"],
+                  one_per_launch_req_per_s=d_1["req_per_s"],
+                  one_per_launch_mpix_per_s=d_1["mpix_per_s"],
+                  speedup=d_b["mpix_per_s"] / d_1["mpix_per_s"])
+    # sustainable rate: the highest offered rate whose p99 meets the objective
+    sweep = []
+    for r in args.serve_sweep:
+        o = run(r, seed + 11, False, args.serve_sweep_seconds)
+        sweep.append(dict(offered=r, served=o["req_per_s"], p50_ms=o["p50_ms"], p99_ms=o["p99_ms"]))
+    ok = [x["offered"] for x in sweep if x["p99_ms"] is not None and x["p99_ms"] <= args.serve_p99_ms]
     low = run(low_rate, seed + 3, True) if low_rate > 0 else None
     rep = run(rate, seed + 1, low is None)
+    rep["served_vs_one_request_per_launch"] = served
+    rep["rate_sweep"] = dict(p99_objective_ms=args.serve_p99_ms, seconds=args.serve_sweep_seconds,
+                             runs=sweep, sustainable_req_per_s=max(ok) if ok else None)
     if low is not None:
         rep["at_lower_rate"] = dict(offered_req_per_s=low_rate, **{
             k: low[k] for k in ("requests", "req_per_s", "mpix_per_s", "p50_ms", "p99_ms",
@@ -585,12 +620,19 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one elementwise kernel that reads and writes 256 MiB (known "
                          "traffic for scaling hardware byte counters)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-drain", type=int, default=120,
+                    help="requests of the batched vs one-request-per-launch comparison")
+    ap.add_argument("--serve-sweep", type=float, nargs="*", default=[60.0, 100.0, 140.0])
+    ap.add_argument("--serve-sweep-seconds", type=float, default=6.0)
+    ap.add_argument("--serve-p99-ms", type=float, default=250.0,
+                    help="p99 latency objective of the sustainable-rate sweep")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-rate-low", type=float, default=60.0,
                     help="a second, lower offered rate (0: skip)")
     ap.add_argument("--serve-sections", type=int, default=30)
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    global args
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the path has no multi-GPU "

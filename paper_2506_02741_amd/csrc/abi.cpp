@@ -132,6 +132,12 @@ struct vtgs_plan {
   };
   std::vector<TrackGraph> graphs;
   uint64_t graph_clock = 0;
+  // the captured mapping iteration (replayed by map_step) and what it was
+  // captured with
+  hipGraphExec_t map_graph = nullptr;
+  vtgs_map_cfg map_cfg{};
+  int32_t *map_step_ptr = nullptr;
+  float *map_loss = nullptr;
   std::vector<hipEvent_t> ev_pool;
   struct EvUse { int stage; size_t start, stop; int launches; };
   std::vector<EvUse> ev_used;  // recorded stage intervals
@@ -363,6 +369,8 @@ int bind_to(vtgs_plan *p, char *ws, const char *h, hipStream_t st) {
   make_ws(p);
   for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
+  if (p->map_graph) (void)hipGraphExecDestroy(p->map_graph);
+  p->map_graph = nullptr;
   HIP_OK(hipMemcpyAsync(p->ws + p->r_desc.off, h, p->desc_bytes, hipMemcpyHostToDevice, st));
   HIP_OK(hipEventRecord(p->upload_done, st));
   HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
@@ -371,6 +379,26 @@ int bind_to(vtgs_plan *p, char *ws, const char *h, hipStream_t st) {
   p->bound = true;
   p->fwd_done = false;
   p->slots_done = false;
+  return VTGS_OK;
+}
+
+// One mapping iteration of every view: forward into the internal images,
+// Eq. 2 and its upstream gradients, backward to the learnable keyframes,
+// Adam steps.
+int map_iteration(vtgs_plan *p, const vtgs_map_cfg &cfg, int32_t *step, float *loss,
+                  hipStream_t st) {
+  const Ws &w = p->w;
+  const int64_t P = p->P;
+  if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
+  STAGE(p, ST_LOSS, st, launch_map_loss(w, cfg, st));
+  if (p->any_learnable) {
+    STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
+    STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr,
+                                               p->any_geo ? 6 : 2, st));
+    p->slots_done = true;
+  }
+  STAGE(p, ST_UPDATE, st,
+        launch_map_update(w, cfg, step, loss, p->any_learnable ? p->max_learn_n : 0, st));
   return VTGS_OK;
 }
 
@@ -586,6 +614,7 @@ void vtgs_plan_destroy(vtgs_plan *p) {
   if (p->pinned) pinned_give(p->pinned, p->pinned_cap);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (p->map_graph) (void)hipGraphExecDestroy(p->map_graph);
   delete p;
 }
 
@@ -804,18 +833,39 @@ int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *l
       if (p->kfs[k].learnable && p->kfs[k].n > 0 && !p->kfs[k].adam)
         return fail(VTGS_E_ARG, "map_step: learnable keyframe " + std::to_string(k) + " has no adam state");
     hipStream_t st = (hipStream_t)stream;
-    const Ws &w = p->w;
-    const int64_t P = p->P;
-    if (int rc = run_forward(p, w.img, w.img + 3 * P, w.img + 4 * P, st)) return rc;
-    STAGE(p, ST_LOSS, st, launch_map_loss(w, *cfg, st));
-    if (p->any_learnable) {
-      STAGE(p, ST_RSCAN, st, launch_scan_records(w, st));
-      STAGE(p, ST_BWD, st, launch_composite_bwd(w, w.gimg, w.gimg + 3 * P, nullptr,
-                                                 p->any_geo ? 6 : 2, st));
-      p->slots_done = true;
+    // Replay the captured iteration when the stream can be captured (not
+    // the legacy default stream), stage timing is off and it was captured
+    // with the same configuration, step counter and loss array (the step
+    // counter lives on the device, so nothing the host writes changes
+    // between replays).
+    const bool graphs = st != nullptr && !p->timing && !std::getenv("VTGS_NO_GRAPH");
+    if (!graphs) return map_iteration(p, *cfg, step, loss, st);
+    if (p->map_graph && (p->map_step_ptr != step || p->map_loss != loss ||
+                         std::memcmp(&p->map_cfg, cfg, sizeof(vtgs_map_cfg)) != 0)) {
+      HIP_OK(hipGraphExecDestroy(p->map_graph));
+      p->map_graph = nullptr;
     }
-    STAGE(p, ST_UPDATE, st,
-          launch_map_update(w, *cfg, step, loss, p->any_learnable ? p->max_learn_n : 0, st));
+    if (!p->map_graph) {
+      HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      const int rc = map_iteration(p, *cfg, step, loss, st);
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &graph);
+      if (rc != VTGS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) return fail(VTGS_E_HIP, std::string("stream capture: ") + hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&p->map_graph, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        p->map_graph = nullptr;
+        return fail(VTGS_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(ei));
+      }
+      p->map_cfg = *cfg;
+      p->map_step_ptr = step;
+      p->map_loss = loss;
+    }
+    HIP_OK(hipGraphLaunch(p->map_graph, st));
     return VTGS_OK;
   } catch (...) {
     return fail(VTGS_E_HIP, "map_step: unexpected exception");

@@ -16,6 +16,14 @@ arrive while a tick runs join at the next tick.  Each view's result depends
 only on its own view (per-view tile lists, per-view twist reductions, no
 atomics on the pose path), so a request's result is the same alone or in
 any mix.
+
+With ``pipeline=True`` the host does not wait for a tick: it builds and
+launches the next tick while the device runs the previous one (two
+workspaces per kind, used by alternate ticks; a tick's track iterations
+follow the previous tick's on the same stream, so poses and Adam states
+carry over on the device).  A tick is retired -- its requests completed,
+their memory released, losses read from pinned host copies -- once its
+events have completed; at most two ticks are in flight.
 """
 from __future__ import annotations
 
@@ -55,7 +63,7 @@ class Server:
     """Continuous batching of render / track requests over one GPU."""
 
     def __init__(self, keyframes, sections, budget_bytes=16 << 30, max_active=64, prm=None,
-                 track_cfg=None, device="cuda"):
+                 track_cfg=None, device="cuda", pipeline=False):
         self.keyframes = keyframes
         self.sections = sections          # list of (kf_first, kf_count)
         self.budget = int(budget_bytes)
@@ -79,6 +87,8 @@ class Server:
         self._est = {}      # workspace estimate per (section, camera, kind)
         self.host_s = 0.0   # building plans and launching, per tick, summed
         self.wait_s = 0.0   # waiting for the device after launching
+        self.pipeline = bool(pipeline)
+        self.inflight = collections.deque()  # launched, not yet retired ticks
 
     # -- admission ---------------------------------------------------------
     def _view_for(self, req):
@@ -139,8 +149,15 @@ class Server:
         self._ws[kind] = plan.ws
         return plan
 
+    def drain(self, now_fn=time.perf_counter):
+        """Retire every tick still in flight (pipelined mode)."""
+        if self.pipeline:
+            self._retire_done(now_fn, block=True, keep=0)
+
     # -- one tick ----------------------------------------------------------
     def tick(self, now_fn=time.perf_counter):
+        if self.pipeline:
+            return self._tick_pipelined(now_fn)
         self._admit(now_fn())
         if not self.active:
             return False
@@ -211,6 +228,106 @@ class Server:
                     r.result = dict(pose=r._view.pose.detach().cpu().numpy().reshape(3, 4),
                                     loss=np.array(r._losses))
 
+    # -- pipelined ticks ------------------------------------------------------
+    def _tick_pipelined(self, now_fn):
+        """Launch a tick over the requests with work left, without waiting
+        for the device; retire completed ticks.  Returns False when nothing
+        was launched and nothing is in flight."""
+        self._retire_done(now_fn, block=False)
+        self._admit(now_fn())
+        rend = [r for r in self.active if r.kind == "render" and r._left > 0]
+        trk = [r for r in self.active if r.kind == "track" and r._left > 0]
+        if not rend and not trk:
+            if self.inflight:
+                self._retire_done(now_fn, block=True, keep=0)
+                return True
+            return False
+        # the workspaces of the tick before last are reused by this one
+        self._retire_done(now_fn, block=True, keep=1)
+        self.batch_sizes.append((len(rend), len(trk)))
+        self.inflight.append(self._launch(rend, trk))
+        self.ticks += 1
+        return True
+
+    def _launch(self, rend, trk):
+        t0 = time.perf_counter()
+        main = torch.cuda.current_stream(self.device)
+        rec = dict(rend=rend, trk=trk, events=[], finishing=[])
+        par = self.ticks % 2
+        if rend:
+            self.s_render.wait_stream(main)
+            with torch.cuda.stream(self.s_render):
+                plan = self._plan(("render", par), [r._view for r in rend])
+                rec["plan_r"] = plan
+                rec["out"] = plan.render_fwd()
+                e = torch.cuda.Event()
+                e.record(self.s_render)
+                rec["events"].append(e)
+            for r in rend:
+                r._left = 0
+                rec["finishing"].append(r)
+        if trk:
+            self.s_track.wait_stream(main)
+            with torch.cuda.stream(self.s_track):
+                plan = self._plan(("track", par), [r._view for r in trk])
+                rec["plan_t"] = plan
+                loss = plan.track_step(self.cfg, 1)
+                host = torch.empty(loss.shape, dtype=loss.dtype, pin_memory=True)
+                host.copy_(loss, non_blocking=True)
+                rec["loss"] = (loss, host)
+                e = torch.cuda.Event()
+                e.record(self.s_track)
+                rec["events"].append(e)
+            for r in trk:
+                r._left -= 1
+                if r._left == 0:
+                    rec["finishing"].append(r)
+        self.host_s += time.perf_counter() - t0
+        return rec
+
+    def _retire_done(self, now_fn, block, keep=None):
+        """Retire the oldest in-flight ticks: those whose events completed
+        (block=False), or as many as needed to leave `keep` in flight."""
+        while self.inflight:
+            rec = self.inflight[0]
+            ready = all(e.query() for e in rec["events"])
+            if not ready:
+                if not block or keep is None or len(self.inflight) <= keep:
+                    return
+                t1 = time.perf_counter()
+                for e in rec["events"]:
+                    e.synchronize()
+                self.wait_s += time.perf_counter() - t1
+            self.inflight.popleft()
+            self._finish(rec, now_fn())
+
+    def _finish(self, rec, t):
+        if rec["rend"]:
+            plan = rec["plan_r"]
+            rc, need = plan.status(clear=True, stream=self.s_render)
+            if rc != 0:
+                raise _lib.VtgsError(rc, _lib.last_error())
+            rgb, depth, sil = rec["out"]
+            for i, r in enumerate(rec["rend"]):
+                r.result = dict(rgb=plan.view_image(rgb, i), depth=plan.view_image(depth, i),
+                                sil=plan.view_image(sil, i))
+        if rec["trk"]:
+            plan = rec["plan_t"]
+            rc, need = plan.status(clear=True, stream=self.s_track)
+            if rc != 0:
+                raise _lib.VtgsError(rc, _lib.last_error())
+            lv = rec["loss"][1][0].numpy()
+            for i, r in enumerate(rec["trk"]):
+                r._losses.append(float(lv[i]))
+        for r in rec["finishing"]:
+            if r.kind == "track":
+                r.result = dict(pose=r._view.pose.detach().cpu().numpy().reshape(3, 4),
+                                loss=np.array(r._losses))
+            r.done = t
+            self.mem_used -= r.ws_bytes
+            self.finished.append(r)
+            self.active.remove(r)
+
     # -- driving a trace -----------------------------------------------------
     def run_trace(self, requests, realtime=True, max_seconds=None):
         """Serve requests whose ``arrival`` times (seconds from start) are set;
@@ -218,7 +335,7 @@ class Server:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0
-        while pending or self.queue or self.active:
+        while pending or self.queue or self.active or self.inflight:
             tnow = now()
             while pending and (pending[0].arrival <= tnow or not realtime):
                 r = pending.popleft()

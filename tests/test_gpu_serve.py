@@ -9,6 +9,10 @@ from scenes import room_frames
 pytestmark = pytest.mark.gpu
 
 
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
 def _requests(serve, cam, frames, n=10, seed=0):
     from paper_2506_02741_amd import synth
     rng = np.random.default_rng(seed)
@@ -49,3 +53,54 @@ def test_serving_alone_equals_mix():
         else:
             assert np.array_equal(a.result["pose"], m.result["pose"]), r.rid
             assert np.array_equal(a.result["loss"], m.result["loss"]), r.rid
+
+
+def test_pipelined_serving_equals_synchronous_and_oracle():
+    """The pipelined server (the host builds and launches the next tick while
+    the device runs the previous one) gives every request the result the
+    synchronous server gives it, bit for bit; served render images match the
+    oracle within 1e-5 (near-ties by their outcomes), and a served track
+    request ends with the pose and losses of the same iterations run by one
+    plan over its view alone."""
+    import torch
+    import oracle as orc
+    from paper_2506_02741_amd import render as R
+    from paper_2506_02741_amd import serve
+    from scenes import oracle_kf
+    from test_gpu_parity import check_images, oracle_ref
+    torch.cuda.set_device(0)
+    cam, frames, _ = room_frames(9, 96, 72, n_kf=4)
+    ks = [R.Keyframe.ingest(f.depth, f.rgb, cam.as_tuple(), f.pose) for f in frames]
+    sections = [(0, 2), (2, 2)]
+    res = {}
+    for pipe in (False, True):
+        srv = serve.Server(ks, sections, budget_bytes=3 * 40 << 20, max_active=6, pipeline=pipe)
+        rep = srv.run_trace(_requests(serve, cam, frames, n=14, seed=2), realtime=False)
+        assert rep["requests"] == 14 and srv.mem_used == 0 and not srv.inflight
+        res[pipe] = {r.rid: r for r in srv.finished}
+    for rid, a in res[False].items():
+        b = res[True][rid]
+        for k in a.result:
+            x, y = a.result[k], b.result[k]
+            assert (torch.equal(x, y) if isinstance(x, torch.Tensor) else np.array_equal(x, y)), (rid, k)
+    okfs = [oracle_kf(orc, f) for f in frames]
+    seen = {"render": 0, "track": 0}
+    for rid, r in sorted(res[True].items()):
+        first, count = sections[r.section]
+        if r.kind == "render" and seen["render"] < 3:
+            ov = orc.ViewSpec(cam.as_tuple(), r.pose, first, count)
+            ref = oracle_ref(orc, ov, okfs)
+            check_images(r.result["rgb"].reshape(3, -1), r.result["depth"].reshape(-1),
+                         r.result["sil"].reshape(-1), ref)
+            seen["render"] += 1
+        elif r.kind == "track" and seen["track"] < 2:
+            # a served track request ends where the same iterations of one
+            # plan over that view alone end (tracking itself is checked
+            # against the oracle per iteration elsewhere)
+            v = R.View(cam.as_tuple(), r.pose, first, count, r.obs_rgb, r.obs_depth).with_pose_adam()
+            p = R.Plan(ks, [v])
+            loss = p.track_step(R.track_cfg(), r.iters)
+            assert np.array_equal(np_(v.pose).reshape(3, 4), r.result["pose"]), rid
+            assert np.array_equal(np_(loss)[:, 0], r.result["loss"].astype(np.float32)), rid
+            seen["track"] += 1
+    assert seen == {"render": 3, "track": 2}, seen

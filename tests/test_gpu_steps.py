@@ -218,6 +218,47 @@ def test_track_graph_replay_equals_eager(R):
     assert np.array_equal(out["graph"][0][0], out["graph"][2][0])
 
 
+def test_map_graph_replay_equals_eager(R):
+    """map_step replays its captured iteration on a non-default stream: four
+    iterations, with eager work and synchronisation between them, give the
+    same parameters, Adam states and losses bit for bit as eager launches
+    (the step counter advances on the device)."""
+    import os
+    import torch
+    cam, frames, _ = room_frames(9, 64, 48, n_kf=2)
+    inp = _section_inputs(frames)
+    out = {}
+    for mode in ("eager", "graph"):
+        ks = [R.Keyframe(cam.as_tuple(), f.pose, d["pix"].astype(np.int32), d["depth"], d["color"],
+                         d["opacity"], d["radius"], learnable=True).with_adam() for f, d in zip(frames, inp)]
+        views = [R.View(cam.as_tuple(), f.pose, 0, 2, f.rgb, f.depth) for f in frames]
+        plan = R.Plan(ks, views)
+        step = torch.zeros(1, dtype=torch.int32, device="cuda")
+        loss = torch.zeros(2, device="cuda")
+        s = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        res = []
+        with torch.cuda.stream(s):
+            for it in range(4):
+                if mode == "eager":
+                    os.environ["VTGS_NO_GRAPH"] = "1"
+                try:
+                    plan.map_step(step, R.map_cfg(), loss)
+                finally:
+                    os.environ.pop("VTGS_NO_GRAPH", None)
+                s.synchronize()
+                res.append(np_(loss).copy())
+                _ = (ks[0].color * 2).sum().item()   # unrelated eager work between replays
+        assert plan.status()[0] == 0 and int(step.item()) == 4
+        out[mode] = (res, [(np_(k.color), np_(k.opacity), np_(k.radius), np_(k.adam)) for k in ks])
+    for a, b in zip(out["eager"][0], out["graph"][0]):
+        assert np.array_equal(a, b)
+    for ka, kb in zip(out["eager"][1], out["graph"][1]):
+        for a, b in zip(ka, kb):
+            assert np.array_equal(a, b)
+    assert not np.array_equal(out["graph"][0][0], out["graph"][0][3])  # it did learn
+
+
 def test_batched_fwd_bwd_graph_replay_equals_eager(R):
     """Forward + backward of a multi-view mapping plan captured once in a
     graph: every replay (with eager work and syncs between replays) gives
@@ -442,3 +483,33 @@ def test_track_two_iterations(R, orc):
         # the next iteration starts from the GPU's state
         pose = np_(view.pose).reshape(3, 4).copy()
         state = dict(m=ad[:6].copy(), v=ad[6:12].copy(), t=t)
+
+
+def test_nonfinite_loss_is_reported(R):
+    """A NaN in a learnable Gaussian's colour makes map_step's Eq. 2 loss
+    non-finite and a NaN in a tracked frame's observed colour makes Eq. 1's:
+    the plan's status reports VTGS_E_NONFINITE, and a cleared flag stays
+    clear on the next clean step."""
+    import torch
+    from paper_2506_02741_amd import _lib
+    cam, frames, _ = room_frames(9, 64, 48, n_kf=2)
+    f = frames[0]
+    k = R.Keyframe.ingest(f.depth, f.rgb, cam.as_tuple(), f.pose, learnable=True).with_adam()
+    k.color[1, 1000] = float("nan")
+    plan = R.Plan([k], [R.View(cam.as_tuple(), f.pose, 0, 1, f.rgb, f.depth)])
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.map_step(step)
+    rc, _ = plan.status()
+    assert rc == _lib.VTGS_E_NONFINITE
+    k2 = R.Keyframe.ingest(f.depth, f.rgb, cam.as_tuple(), f.pose)
+    obs = f.rgb.copy()
+    obs[0, 24, 32] = np.nan
+    view = R.View(cam.as_tuple(), frames[1].pose, 0, 1, obs, f.depth).with_pose_adam()
+    tp = R.Plan([k2], [view])
+    tp.track_step(R.track_cfg(), 1)
+    assert tp.status()[0] == _lib.VTGS_E_NONFINITE
+    assert tp.status()[0] == _lib.VTGS_OK            # cleared by the first status
+    clean = R.View(cam.as_tuple(), frames[1].pose, 0, 1, f.rgb, f.depth).with_pose_adam()
+    cp = R.Plan([k2], [clean])
+    cp.track_step(R.track_cfg(), 2)
+    assert cp.status()[0] == _lib.VTGS_OK

@@ -1,6 +1,7 @@
 // C ABI of the gfx950 view-tied splatting library (declared in vtgs.h):
 // argument validation, plans (descriptor tables and workspace layout) and
 // the launch sequences of render_fwd, render_bwd, track_step and map_step.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,9 +106,10 @@ struct vtgs_plan {
   int32_t max_learn_n = 0;
   bool any_learnable = false;
   bool any_geo = false;  // a learnable keyframe wants depth / pose gradients
+  bool tile_order = false;  // composite the longest tile lists first
   // workspace layout
   Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
-      r_ranges, r_long, r_keys, r_keys_tmp, r_ids, r_slots, r_kpose, r_bits, r_tfinal, r_last,
+      r_ranges, r_long, r_order, r_keys, r_keys_tmp, r_ids, r_slots, r_kpose, r_bits, r_tfinal, r_last,
       r_img, r_gimg, r_twist, r_loss, r_ssim_map, r_ssim_part;
   int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
   std::vector<char> desc_host;  // the descriptor tables as laid out in the workspace
@@ -190,6 +192,7 @@ void layout(vtgs_plan *p) {
   take(p->r_tfill, nt * 4);
   take(p->r_ranges, nt * 8);
   take(p->r_long, nt * 4);
+  take(p->r_order, nt * 4);
   take(p->r_keys, cap * 8);
   take(p->r_keys_tmp, cap * 8);
   take(p->r_ids, cap * 4);
@@ -223,6 +226,7 @@ void make_ws(vtgs_plan *p) {
   w.n_long = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 24);
   w.long_next = reinterpret_cast<uint32_t *>(b + p->r_hdr.off + 28);
   w.long_tiles = at<uint32_t>(b, p->r_long);
+  w.tile_order = p->tile_order ? at<uint32_t>(b, p->r_order) : nullptr;
   char *d = b + p->r_desc.off;
   w.kfs = reinterpret_cast<const DevKF *>(d + p->desc_kf);
   w.views = reinterpret_cast<const DevView *>(d + p->desc_view);
@@ -292,6 +296,39 @@ int check_bound(vtgs_plan *p) {
   return VTGS_OK;
 }
 
+// Optional roctx ranges (VTGS_ROCTX=1): one per entry point call and one per
+// stage launch, named after them, so that a rocprofv3 --marker-trace puts
+// the kernels of a trace under their entry point and stage.  The roctx
+// library is opened at the first call only when asked for, so the library
+// has no link-time dependency on it.
+struct Roctx {
+  int (*push)(const char *) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char *e = std::getenv("VTGS_ROCTX");
+    if (!e || std::atoi(e) == 0) return x;
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) return x;
+    x.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+    x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+    if (!x.push || !x.pop) x.push = nullptr, x.pop = nullptr;
+    return x;
+  }();
+  return r;
+}
+struct RoctxRange {
+  bool on;
+  explicit RoctxRange(const char *name) : on(roctx().push != nullptr) {
+    if (on) roctx().push(name);
+  }
+  ~RoctxRange() {
+    if (on) roctx().pop();
+  }
+};
+
 enum Stage {
   ST_PRE, ST_SCAN, ST_FILL, ST_SORT, ST_FWD, ST_LOSS, ST_RSCAN, ST_BWD, ST_REDUCE, ST_UPDATE, ST_N
 };
@@ -326,7 +363,10 @@ hipError_t event_at(vtgs_plan *p, size_t i, hipEvent_t *e) {
       HIP_OK(hipEventRecord(ev_, (st)));                                          \
       if ((stg) == ST_FWD || (stg) == ST_BWD) rep_ = (p)->timing_repeat;         \
     }                                                                            \
-    for (int r_ = 0; r_ < rep_; r_++) HIP_OK(expr);                             \
+    {                                                                            \
+      RoctxRange rr_(kStageNames[(stg)]);                                        \
+      for (int r_ = 0; r_ < rep_; r_++) HIP_OK(expr);                           \
+    }                                                                            \
     if ((p)->timing) {                                                           \
       hipEvent_t ev_;                                                             \
       HIP_OK(event_at((p), i0_ + 1, &ev_));                                       \
@@ -449,6 +489,7 @@ int vtgs_ingest_fill(const float *depth_img, const float *rgb_img, const uint8_t
                      int32_t H, int32_t W, int32_t stride, float fx, float o_init,
                      const void *scratch, int64_t scratch_bytes, int32_t n, uint32_t *pix,
                      float *depth, float *color, float *opacity, float *radius, void *stream) {
+  RoctxRange rr_("vtgs_ingest_fill");
   try {
     if (!depth_img || !scratch) return fail(VTGS_E_ARG, "ingest_fill: NULL pointer");
     if (n > 0 && (!pix || !depth || !opacity || !radius || (rgb_img && !color)))
@@ -575,6 +616,12 @@ int vtgs_plan_create(const vtgs_keyframe *kfs, int32_t n_kf, const vtgs_view *vi
     p->n_rec = (int32_t)n_rec;
     p->n_tiles = (int32_t)n_tiles;
     p->P = Ptot;
+    // longest tile lists first where views of different sizes and list
+    // lengths share a grid (a multi-view plan); VTGS_TILE_ORDER=0 / 1 forces it
+    {
+      const char *e = std::getenv("VTGS_TILE_ORDER");
+      p->tile_order = e ? std::atoi(e) != 0 : n_views > 1;
+    }
     p->loss_blocks = std::max(loss_blocks, 1);
     p->ssim_gx = (maxw + 15) / 16;
     p->ssim_gy = (maxh + 15) / 16;
@@ -620,6 +667,7 @@ void vtgs_plan_destroy(vtgs_plan *p) {
 
 int vtgs_uncovered_mask(const float *sil, const float *depth_img, int64_t n, float thr,
                         uint8_t *mask, void *stream) {
+  RoctxRange rr_("vtgs_uncovered_mask");
   try {
     if (n < 0 || (n > 0 && (!sil || !depth_img || !mask)))
       return fail(VTGS_E_ARG, "uncovered_mask: need n >= 0 and non-NULL arrays");
@@ -685,6 +733,7 @@ int vtgs_plan_status(vtgs_plan *p, int64_t *pairs_needed, int32_t clear, void *s
 }
 
 int vtgs_render_fwd(vtgs_plan *p, float *rgb, float *depth, float *sil, void *stream) {
+  RoctxRange rr_("vtgs_render_fwd");
   try {
     if (int rc = check_bound(p)) return rc;
     return run_forward(p, rgb, depth, sil, (hipStream_t)stream);
@@ -694,6 +743,7 @@ int vtgs_render_fwd(vtgs_plan *p, float *rgb, float *depth, float *sil, void *st
 }
 
 int vtgs_render_fwd_static(vtgs_plan *p, float *rgb, float *depth, float *sil, void *stream) {
+  RoctxRange rr_("vtgs_render_fwd_static");
   try {
     if (!p) return fail(VTGS_E_ARG, "render_fwd_static: plan is NULL");
     if (p->ws_bytes > (int64_t)VTGS_STATIC_SCRATCH_BYTES)
@@ -728,6 +778,7 @@ int vtgs_render_fwd_static(vtgs_plan *p, float *rgb, float *depth, float *sil, v
 
 int vtgs_render_bwd(vtgs_plan *p, const float *g_rgb, const float *g_depth, const float *g_sil,
                     float *g_twist, void *stream) {
+  RoctxRange rr_("vtgs_render_bwd");
   try {
     if (int rc = check_bound(p)) return rc;
     if (!p->fwd_done) return fail(VTGS_E_ARG, "render_bwd: no render_fwd on this plan yet");
@@ -754,6 +805,7 @@ int vtgs_render_bwd(vtgs_plan *p, const float *g_rgb, const float *g_depth, cons
 
 int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, float *loss,
                     void *stream) {
+  RoctxRange rr_("vtgs_track_step");
   try {
     if (int rc = check_bound(p)) return rc;
     if (!cfg) return fail(VTGS_E_ARG, "track_step: cfg is NULL");
@@ -821,6 +873,7 @@ int vtgs_track_step(vtgs_plan *p, const vtgs_track_cfg *cfg, int32_t iters, floa
 
 int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *loss,
                   void *stream) {
+  RoctxRange rr_("vtgs_map_step");
   try {
     if (int rc = check_bound(p)) return rc;
     if (!cfg || !step) return fail(VTGS_E_ARG, "map_step: cfg and step are required");
@@ -875,6 +928,7 @@ int vtgs_map_step(vtgs_plan *p, const vtgs_map_cfg *cfg, int32_t *step, float *l
 int vtgs_visibility(const float *src_depth, const vtgs_camera *src_cam, const float *src_pose,
                     const vtgs_frame_ref *targets, int32_t n_targets, float rel_tol, float z_near,
                     uint8_t *mask, int32_t *counts, void *stream) {
+  RoctxRange rr_("vtgs_visibility");
   try {
     if (!src_depth || !src_cam || !src_pose || !targets || n_targets < 1)
       return fail(VTGS_E_ARG, "visibility: need the source arrays and n_targets >= 1 targets");

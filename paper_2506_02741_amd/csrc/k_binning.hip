@@ -219,6 +219,15 @@ constexpr int kSmallSort = 768;  // longer tile lists go to the long-list sort
 // long-list sort (queue and its cursor reset here); clears the counters for
 // the next pass.
 constexpr int kScanNT = 1024, kScanPer = 8;
+constexpr int kOrderBuckets = 64;
+// Bucket of a list of n entries in the longest-first order: 0 for the
+// longest, two per octave (bit length and the next bit), 63 for empty.
+__device__ __forceinline__ int order_bucket(uint32_t n) {
+  if (n == 0u) return kOrderBuckets - 1;
+  const int bl = 32 - __clz((int)n);                              // 1 .. 32
+  const int sb = bl >= 2 ? (int)((n >> (bl - 2)) & 1u) : 0;
+  return kOrderBuckets - 2 - min(2 * bl + sb - 2, kOrderBuckets - 2);
+}
 __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
   __shared__ uint32_t lw[kScanNT / kWave];
   __shared__ unsigned long long carry_s;
@@ -257,6 +266,30 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
     if (carry_s > (unsigned long long)ws.cap) atomicOr(ws.flags, kFlagCapacity);
     *ws.n_long = nlong_s;
     *ws.long_next = 0u;
+  }
+  if (ws.tile_order) {
+    // longest lists first: tiles bucketed by list length (two buckets per
+    // octave, longest first, empty lists last), so that the compositing
+    // grid, dispatched in block order, starts its heaviest tiles first and
+    // ends on light ones; the order within a bucket is whatever the atomics
+    // give (each tile's results do not depend on it)
+    __shared__ uint32_t bk[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) bk[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < ws.n_tiles; i += kScanNT)
+      atomicAdd(&bk[order_bucket(ws.ranges[i].y - ws.ranges[i].x)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t run = 0u;
+      for (int b = 0; b < kOrderBuckets; b++) {
+        const uint32_t c = bk[b];
+        bk[b] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ws.n_tiles; i += kScanNT)
+      ws.tile_order[atomicAdd(&bk[order_bucket(ws.ranges[i].y - ws.ranges[i].x)], 1u)] = (uint32_t)i;
   }
 }
 
@@ -696,42 +729,43 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, ui
   for (int i = l; i < n; i += kWave) dst[i] = (uint32_t)buf[lds_pos(i)];
 }
 
-// Bitonic sort with ascending comparators only (a flip stage then
-// half-cleaners), so indices >= n behave as +infinity and need no padding.
-// Used in global memory for tiles longer than the LDS capacity.
-template <typename T>
-__device__ __forceinline__ void bitonic_sort(T *s, int n) {
-  int np = 1;
-  while (np < n) np <<= 1;
-  for (int k = 2; k <= np; k <<= 1) {
-    const int half = k >> 1;
-    for (int c = threadIdx.x; c < np / 2; c += blockDim.x) {
-      const int i = (c / half) * k + (c % half);
-      const int p = i + (k - 1 - 2 * (c % half));
-      if (p < n) {
-        const auto x = s[i], y = s[p];
-        if (y < x) { s[i] = y; s[p] = x; }
-      }
+// One round of a merge sort over n keys held as sorted runs of `width`
+// keys in `in`: each pair of neighbouring runs is merged into `out` (an odd
+// run at the end is copied), written as D (u64: the keys, u32: the ids).
+// Every thread takes an equal share of each merged pair's output, finds
+// where its share starts by a binary search along the merge path, and
+// merges its share serially.  Keys are unique and below ~0, so ~0 serves
+// as the end of either run.
+template <int NT, typename D>
+__device__ void merge_round(const unsigned long long *in, D *out, int n, int width) {
+  for (int lo = 0; lo < n; lo += 2 * width) {
+    const int mid = min(lo + width, n), hi = min(lo + 2 * width, n);
+    const unsigned long long *A = in + lo, *B = in + mid;
+    const int la = mid - lo, lb = hi - mid, m = hi - lo;
+    const int d0 = (int)((int64_t)m * threadIdx.x / NT);
+    const int d1 = (int)((int64_t)m * (threadIdx.x + 1) / NT);
+    // the first d0 outputs are A[0, i) and B[0, d0 - i)
+    int a = max(0, d0 - lb), b = min(d0, la);
+    while (a < b) {
+      const int md = (a + b) >> 1;
+      if (A[md] < B[d0 - md - 1]) a = md + 1;
+      else b = md;
     }
-    __syncthreads();
-    for (int j = half >> 1; j > 0; j >>= 1) {
-      for (int c = threadIdx.x; c < np / 2; c += blockDim.x) {
-        const int i = (c / j) * 2 * j + (c % j);
-        const int p = i + j;
-        if (p < n) {
-          const auto x = s[i], y = s[p];
-          if (y < x) { s[i] = y; s[p] = x; }
-        }
-      }
-      __syncthreads();
+    int i = a, j = d0 - a;
+    unsigned long long va = i < la ? A[i] : ~0ull, vb = j < lb ? B[j] : ~0ull;
+    for (int d = d0; d < d1; d++) {
+      const bool ta = va < vb;
+      out[lo + d] = (D)(ta ? va : vb);
+      if (ta) { i++; va = i < la ? A[i] : ~0ull; }
+      else { j++; vb = j < lb ? B[j] : ~0ull; }
     }
   }
 }
 
-// Sort of one tile's n keys with EE keys per thread (n <= NT * EE), the ids
-// written to dst in ascending key order.
-template <int NT, int EE>
-__device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, uint32_t *dst, int n,
+// Sort of one tile's n keys with EE keys per thread (n <= NT * EE), written
+// to dst in ascending key order as D (u32: the ids, u64: the keys).
+template <int NT, int EE, typename D>
+__device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, D *dst, int n,
                                                unsigned long long *buf, uint32_t (*wsum)[8],
                                                unsigned long long *red, uint32_t *starts) {
   unsigned long long k[EE];
@@ -742,7 +776,7 @@ __device__ __forceinline__ void sort_tile_regs(const unsigned long long *src, ui
 #pragma unroll
   for (int e = 0; e < EE; e++) k[e] = (int)threadIdx.x + NT * e < n ? k[e] : ~0ull;
   block_sort_u64<NT, EE>(k, n, buf, wsum, red, starts);
-  for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)buf[lds_pos(i)];
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = (D)buf[lds_pos(i)];
 }
 
 // Register tiers of the tile sort: keys per thread for a one-wave block
@@ -800,23 +834,38 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, in
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
     continue;
   }
-  bool done = true;
   if constexpr (kWaveSort) {
     if (n <= NT * E1) wave_sort_tile<E1>(src, dst, n, buf, starts);
     else if (n <= CAP) wave_sort_tile<E>(src, dst, n, buf, starts);
-    else done = false;
   } else {
     if (n <= NT * E1) sort_tile_regs<NT, E1>(src, dst, n, buf, wsum, red, starts);
     else if (n <= NT * E2) sort_tile_regs<NT, E2>(src, dst, n, buf, wsum, red, starts);
     else if (n <= CAP) sort_tile_regs<NT, E>(src, dst, n, buf, wsum, red, starts);
-    else done = false;
-  }
-  if (!done) {
-    unsigned long long *g = ws.keys_tmp + rg.x;
-    for (int i = threadIdx.x; i < n; i += NT) g[i] = src[i];
-    __syncthreads();
-    bitonic_sort(g, n);
-    for (int i = threadIdx.x; i < n; i += NT) dst[i] = (uint32_t)g[i];
+    else {
+      // longer than the LDS holds: runs of CAP keys sorted in LDS into
+      // keys_tmp, then merged pairwise, back and forth between keys_tmp and
+      // the tile's own key range (free once its runs are sorted); the last
+      // round writes the ids
+      unsigned long long *runs = ws.keys_tmp + rg.x, *spare = ws.keys + rg.x;
+      for (int lo = 0; lo < n; lo += CAP) {
+        const int c = min(CAP, n - lo);
+        if (c <= NT * E1) sort_tile_regs<NT, E1>(src + lo, runs + lo, c, buf, wsum, red, starts);
+        else if (c <= NT * E2) sort_tile_regs<NT, E2>(src + lo, runs + lo, c, buf, wsum, red, starts);
+        else sort_tile_regs<NT, E>(src + lo, runs + lo, c, buf, wsum, red, starts);
+        __syncthreads();  // buf is reused by the next run
+      }
+      const unsigned long long *in = runs;
+      unsigned long long *out = spare;
+      int width = CAP;
+      for (; 2 * width < n; width *= 2) {
+        merge_round<NT>(in, out, n, width);
+        __syncthreads();
+        unsigned long long *nxt = const_cast<unsigned long long *>(in);
+        in = out;
+        out = nxt;
+      }
+      merge_round<NT>(in, dst, n, width);
+    }
   }
   __syncthreads();  // buf is reused by the block's next tile
   }

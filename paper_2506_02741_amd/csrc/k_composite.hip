@@ -50,6 +50,8 @@
 // sums go to the pair's (record, tile) slot, and a gather pass sums a
 // record's slots.  Neither mode uses global
 // atomics and no two waves share an accumulator, so both are deterministic.
+#include <type_traits>
+
 #include "vtgs_internal.h"
 
 namespace vtgs {
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_fwd(Ws ws, float *out_rgb, 
   __shared__ float4 e0s[BATCH], e1s[BATCH], e2s[BATCH];
   __shared__ unsigned long long masks[NW][NCH];
   __shared__ uint32_t words[NS][NR][kWave];
-  const int t = blockIdx.x;
+  const int t = tile_of_block(ws);
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
   const int lt = t - vw.tile_base;
   const int ox = (lt % vw.tiles_x) * TILE, oy = (lt / vw.tiles_x) * TILE;
@@ -435,8 +437,22 @@ __device__ __forceinline__ uint32_t entry_slot(const Ws &ws, const BwdEntry &E, 
   return E.ok && sl < (uint64_t)ws.cap ? sl : 0xffffffffu;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// LDS pointers
+#define LDS_AS __attribute__((address_space(3)))
+// An empty statement that the compiler must take as reading and writing all
+// memory: LDS accesses keep their program order across it (and the LDS
+// keeps a wave's order).
+__device__ __forceinline__ void kLdsOrder() { asm volatile("" ::: "memory"); }
+// The accumulator floats past the first four: one (dL/dr) or, with
+// geometry, four (dL/dr, dL/dp).
+template <bool kGeo>
+using AccB = typename std::conditional<kGeo, f32x4, float>::type;
+
+// Slot modes hold three waves per SIMD (their LDS allows three blocks per CU)
+// unless they carry geometry (two).
 template <int TILE, int BATCH, int MODE>
-__global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_rgb,
+__global__ __launch_bounds__(Shape<TILE>::NT, (MODE & 2) ? ((MODE & 4) ? 2 : 3) : 1) void k_bwd(Ws ws, const float *g_rgb,
                                                          const float *g_depth,
                                                          const float *g_sil, TrackArgs tr) {
   constexpr int NT = Shape<TILE>::NT, PPT = Shape<TILE>::PPT;
@@ -453,13 +469,17 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
   __shared__ float4 ejs[BATCH];   // (fx/z, fy/z, -fx px/z^2, -fy py/z^2)
   __shared__ float4 eps_[BATCH];  // (px, py, 2 r^2 / z, learnable)
   __shared__ uint32_t slot_s[AB];
-  __shared__ float acc[NW][NA][AB];
+  // per-wave slot accumulators: floats 0-3 in accA, 4 (4-7 with geometry)
+  // in accB, and the claim tags of their read-modify-write
+  __shared__ f32x4 accA[NW][AB];
+  __shared__ AccB<kGeo> accB[NW][AB];
+  __shared__ uint8_t tag_s[kSlots ? NW : 1][AB + kWave];  // + a tag per lane
   __shared__ int maxlast_s;
   __shared__ float red_s[NW][7];
   __shared__ unsigned long long masks[NW][NCH];
   __shared__ uint32_t words[NS][NR][kWave];
 
-  const int t = blockIdx.x;
+  const int t = tile_of_block(ws);
   const DevView &vw = ws.views[find_view_by_tile(ws, t)];
   const int lt = t - vw.tile_base;
   const int tx = lt % vw.tiles_x, ty = lt / vw.tiles_x;
@@ -579,9 +599,10 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       if (kSlots) {
         slot_s[i] = sl;
 #pragma unroll
-        for (int ww = 0; ww < NW; ww++)
-#pragma unroll
-          for (int c = 0; c < NA; c++) acc[ww][c][i] = 0.f;
+        for (int ww = 0; ww < NW; ww++) {
+          accA[ww][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+          accB[ww][i] = AccB<kGeo>{};
+        }
       }
     }
     __syncthreads();
@@ -645,14 +666,55 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
         // the next entry's LDS reads are issued before this one is replayed
         int i = gb + (int)((sq & 15u) << 5) - low_bit(cur);
         float4 n0 = e0s[i], n1 = e1s[i], n2 = e2s[i], nj = ejs[i], np = eps_[i];
-        while (cur != 0u) {
+        // Slots (mapping): each lane's adds of a step go into its wave's
+        // accumulators by read-modify-write.  The lanes that replay one
+        // entry in a step claim it by writing their lane number to its tag;
+        // with the claim they read the tag back and the accumulators.  The
+        // claim is settled in the lane's next step, after that step's
+        // arithmetic has covered the reads' latency: the lane whose number
+        // stayed in the tag (one per entry) adds what it read to its values
+        // and writes them back, before any new claim is made.  A lane that
+        // lost claims the same entry again in that step, keeps the values of
+        // the step it just computed waiting, and computes nothing in its next
+        // step; a lane runs idle steps after its last entry until its claims
+        // are settled.  (Two lanes replay one entry in the same step in about
+        // two steps of three of a mapping wave, 6 % of the lane steps.)  LDS
+        // float atomics would do the same adds at a far lower rate.  Compiler
+        // barriers (kLdsOrder) keep each claim and settle in its step and in
+        // program order.
+        bool pp = false;  // an open claim (values pva/pvb for entry pidx)
+        bool hq = false;  // values waiting to be claimed (qva/qvb for qidx)
+        int pidx = 0, qidx = 0, rt = 0;
+        f32x4 pva = {0.f, 0.f, 0.f, 0.f}, ra = {0.f, 0.f, 0.f, 0.f}, qva = {0.f, 0.f, 0.f, 0.f};
+        AccB<kGeo> pvb{}, rb{}, qvb{};
+        const int me = lane_id();
+        // a claim: tag slot `ti` claimed, then read back with entry j's
+        // accumulators
+        auto claim = [&](int ti, int j) {
+          uint8_t LDS_AS *tg = (uint8_t LDS_AS *)&tag_s[w][ti];
+          *tg = (uint8_t)me;
+          kLdsOrder();
+          rt = *tg;
+          ra = *(f32x4 LDS_AS *)&accA[w][j];
+          rb = *(AccB<kGeo> LDS_AS *)&accB[w][j];
+          kLdsOrder();
+        };
+        // the loop is entered, as it is re-entered, with a claim's LDS
+        // operations behind the first entry's reads (here one on the lane's
+        // own tag, not settled)
+        if constexpr (kSlots) claim(AB + me, 0);
+        while (cur != 0u || (kSlots && (pp || hq))) {
+          const bool live = !kSlots || (cur != 0u && !hq);
           const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
           const int cur_i = i;  // this entry's batch position
-          cur &= cur - 1u;
-          const bool z = cur == 0u;
-          cur = z ? nxt : cur;
-          sq = z ? sq >> 4 : sq;
-          sp += z ? 1u : 0u;
+          {
+            uint32_t c2 = cur & (cur - 1u);
+            const bool z = c2 == 0u;
+            c2 = z ? nxt : c2;
+            cur = live ? c2 : cur;
+            sq = live && z ? sq >> 4 : sq;
+            sp += live && z ? 1u : 0u;
+          }
           nxt = words[sp + 1u][row][lane_id()];
           i = gb + (int)((sq & 15u) << 5) - low_bit(cur);
           n0 = e0s[i]; n1 = e1s[i]; n2 = e2s[i]; nj = ejs[i]; np = eps_[i];
@@ -660,7 +722,7 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
           const float q = quad2(e0, e1.x, px[k], py[k]);
           const float gau = __builtin_amdgcn_exp2f(q * kNegHalfLog2e);
           const float a = fminf(amax, e1.y * gau);
-          const bool ok = a >= amin;
+          const bool ok = live && a >= amin;
           const float oG = e1.y * gau;
           const float om = 1.0f - a;
           const float Tk = ok ? T[k] * __builtin_amdgcn_rcpf(om) : T[k];
@@ -692,26 +754,60 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
             const float s2 = fmaf(t0, t0, fmaf(t1, t1, 2.0f * t2 * t2));
             g2v = fmaf(dLdq, fmaf(kk, s2, -2.0f * t2), wgt * gD[k]);
           }
-          if (kTwist) {
+          if (kTwist && live) {
             const float pz = e1.z;
             tw[0] += g0v; tw[1] += g1v; tw[2] += g2v;
             tw[3] += ep.y * g2v - pz * g1v;
             tw[4] += pz * g0v - ep.x * g2v;
             tw[5] += ep.x * g1v - ep.y * g0v;
           }
-          if (kSlots && ok && ep.w != 0.f) {
-            // this wave's accumulators: only its own lanes add to them
+          if constexpr (kSlots) {
+            // this step's values
+            const bool real = ok && ep.w != 0.f;
             const float tt = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
-            atomicAdd(&acc[w][0][cur_i], wgt * gC0[k]);
-            atomicAdd(&acc[w][1][cur_i], wgt * gC1[k]);
-            atomicAdd(&acc[w][2][cur_i], wgt * gC2[k]);
-            atomicAdd(&acc[w][3][cur_i], pass ? gau * dLda : 0.f);
-            atomicAdd(&acc[w][4][cur_i], dLdq * (-2.0f * e2.w * tt));
-            if (kGeo) {
-              atomicAdd(&acc[w][5][cur_i], g0v);
-              atomicAdd(&acc[w][6][cur_i], g1v);
-              atomicAdd(&acc[w][7][cur_i], g2v);
+            const f32x4 nva = {wgt * gC0[k], wgt * gC1[k], wgt * gC2[k], pass ? gau * dLda : 0.f};
+            const float v4 = dLdq * (-2.0f * e2.w * tt);
+            AccB<kGeo> nvb;
+            if constexpr (kGeo) nvb = f32x4{v4, g0v, g1v, g2v};
+            else nvb = v4;
+            // the settle below waits for the previous claim's reads: after
+            // the step's arithmetic (which this empty statement consumes)
+            asm volatile("" ::"v"(nva[0]), "v"(nva[1]), "v"(nva[2]), "v"(nva[3]), "v"(v4) : "memory");
+            // settle the previous step's claim: the lane whose number stayed
+            // in the tag writes its sum back
+            const bool won = pp && rt == me;
+            if (won) {
+              *(f32x4 LDS_AS *)&accA[w][pidx] = ra + pva;
+              *(AccB<kGeo> LDS_AS *)&accB[w][pidx] = rb + pvb;
             }
+            kLdsOrder();
+            pp = pp && !won;
+            // what this step claims: a claim that lost, again (this step's
+            // values then wait, and the lane computes nothing next step); else
+            // the waiting values; else this step's
+            if (pp) {
+              if (real) {
+                hq = true;
+                qva = nva;
+                qvb = nvb;
+                qidx = cur_i;
+              }
+            } else if (hq) {
+              pp = true;
+              pva = qva;
+              pvb = qvb;
+              pidx = qidx;
+              hq = false;
+            } else if (real) {
+              pp = true;
+              pva = nva;
+              pvb = nvb;
+              pidx = cur_i;
+            }
+            // every lane claims (a lane with nothing to claim its own tag), so
+            // that the LDS operations behind the next entry's reads are the
+            // same on every path and the next step waits for those reads only
+            claim(pp ? pidx : AB + me, pp ? pidx : cur_i);
           }
         }
       }
@@ -721,12 +817,20 @@ __global__ __launch_bounds__(Shape<TILE>::NT) void k_bwd(Ws ws, const float *g_r
       for (int i = threadIdx.x; i < nb; i += NT) {
         if (eps_[i].w == 0.f) continue;
         float *o = ws.slots + NA * (int64_t)slot_s[i];
+        f32x4 sa = accA[0][i];
+        AccB<kGeo> sb = accB[0][i];
 #pragma unroll
-        for (int c = 0; c < NA; c++) {
-          float s = 0.f;
+        for (int ww = 1; ww < NW; ww++) {
+          sa = sa + accA[ww][i];
+          sb = sb + accB[ww][i];
+        }
 #pragma unroll
-          for (int ww = 0; ww < NW; ww++) s += acc[ww][c][i];
-          o[c] = s;
+        for (int c = 0; c < 4; c++) o[c] = sa[c];
+        if constexpr (kGeo) {
+#pragma unroll
+          for (int c = 0; c < 4; c++) o[4 + c] = sb[c];
+        } else {
+          o[4] = sb;
         }
       }
     }

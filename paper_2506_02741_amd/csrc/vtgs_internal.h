@@ -74,6 +74,7 @@ struct Ws {
   uint32_t *n_long;            // tiles with lists longer than the short-list sort takes
   uint32_t *long_next;         // cursor of the long-list sort over long_tiles
   uint32_t *long_tiles;        // [n_tiles] those tiles (written by the tile scan)
+  uint32_t *tile_order;        // [n_tiles] compositing order, longest lists first (NULL: tile order)
   // descriptors
   const DevKF *kfs;
   const DevView *views;
@@ -205,6 +206,12 @@ __device__ __forceinline__ int find_view_by_record(const Ws &ws, int r) {
     if (ws.views[mid].rec_base <= r) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// The tile a compositing block takes: the scan's longest-first order when
+// the plan has one, else the block's own index.
+__device__ __forceinline__ int tile_of_block(const Ws &ws) {
+  return ws.tile_order ? (int)ws.tile_order[blockIdx.x] : (int)blockIdx.x;
 }
 
 __device__ __forceinline__ int find_view_by_tile(const Ws &ws, int t) {

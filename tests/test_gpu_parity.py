@@ -472,20 +472,23 @@ def test_autograd_matches_oracle_and_fd(R, orc):
             assert abs(fd - float(k.opacity.grad[i])) <= 2e-2 * max(1.0, abs(fd)), (fd, float(k.opacity.grad[i]))
 
 
-@pytest.mark.parametrize("zoom,tile", [(2.5, 16), (4.0, 32), (8.0, 32)])
-def test_long_tile_lists_bitwise(R, orc, zoom, tile):
+@pytest.mark.parametrize("zoom,tile,n_kf", [(2.5, 16, 3), (4.0, 32, 3), (8.0, 32, 3), (8.0, 16, 5),
+                                             (12.0, 32, 5)])
+def test_long_tile_lists_bitwise(R, orc, zoom, tile, n_kf):
     """A zoomed-out view puts several keyframes' Gaussians into few tiles, so
-    tile lists exceed the short-list sort (2048) and, at the largest zoom,
-    the LDS capacity (8192, sorted in global memory)."""
-    cam, frames, vpose = room_frames(9, 96, 72, n_kf=3)
+    tile lists exceed the short-list sort (768) and, from zoom 8, the LDS
+    capacity (8192: runs of 8192 sorted in LDS, then merged in rounds).  The
+    zoom-8 cases hold lists of 1 to 3 runs (up to 23,902 entries), the
+    zoom-12 one a list of 34,560 (5 runs: three rounds, an odd run copied)."""
+    cam, frames, vpose = room_frames(9, 96, 72, n_kf=n_kf)
     ks = [gpu_kf(R, fr) for fr in frames]
     c = (cam.fx / zoom, cam.fy / zoom, cam.cx, cam.cy, cam.width, cam.height)
-    plan = R.Plan(ks, [R.View(c, vpose, 0, 3)], R.params(tile=tile))
+    plan = R.Plan(ks, [R.View(c, vpose, 0, n_kf)], R.params(tile=tile))
     imgs = plan.render_fwd()
     st = plan.debug_state()
     assert plan.status()[0] == 0
     okfs = [oracle_kf(orc, f) for f in frames]
-    ov = orc.ViewSpec(c, vpose, 0, 3)
+    ov = orc.ViewSpec(c, vpose, 0, n_kf)
     prm = orc.params(tile=tile)
     keys, vals, ranges = orc.tile_lists(ov, okfs, prm)
     lens = ranges[:, 1] - ranges[:, 0]

@@ -673,20 +673,16 @@ __global__ __launch_bounds__(Shape<TILE>::NT, (MODE & 2) ? ((MODE & 4) ? 2 : 3) 
         // claim is settled in the lane's next step, after that step's
         // arithmetic has covered the reads' latency: the lane whose number
         // stayed in the tag (one per entry) adds what it read to its values
-        // and writes them back, before any new claim is made.  A lane that
-        // lost claims the same entry again in that step, keeps the values of
-        // the step it just computed waiting, and computes nothing in its next
-        // step; a lane runs idle steps after its last entry until its claims
-        // are settled.  (Two lanes replay one entry in the same step in about
-        // two steps of three of a mapping wave, 6 % of the lane steps.)  LDS
-        // float atomics would do the same adds at a far lower rate.  Compiler
-        // barriers (kLdsOrder) keep each claim and settle in its step and in
-        // program order.
+        // and writes them back, and the lanes that lost then add theirs with
+        // LDS float atomics (6 % of the lane steps of a mapping wave, against
+        // all of them with atomics alone, which the LDS runs at about a lane
+        // per three clocks).  A lane runs one idle step after its last entry
+        // to settle its last claim.  Compiler barriers (kLdsOrder) keep each
+        // claim and settle in its step and in program order.
         bool pp = false;  // an open claim (values pva/pvb for entry pidx)
-        bool hq = false;  // values waiting to be claimed (qva/qvb for qidx)
-        int pidx = 0, qidx = 0, rt = 0;
-        f32x4 pva = {0.f, 0.f, 0.f, 0.f}, ra = {0.f, 0.f, 0.f, 0.f}, qva = {0.f, 0.f, 0.f, 0.f};
-        AccB<kGeo> pvb{}, rb{}, qvb{};
+        int pidx = 0, rt = 0;
+        f32x4 pva = {0.f, 0.f, 0.f, 0.f}, ra = {0.f, 0.f, 0.f, 0.f};
+        AccB<kGeo> pvb{}, rb{};
         const int me = lane_id();
         // a claim: tag slot `ti` claimed, then read back with entry j's
         // accumulators
@@ -703,8 +699,8 @@ __global__ __launch_bounds__(Shape<TILE>::NT, (MODE & 2) ? ((MODE & 4) ? 2 : 3) 
         // operations behind the first entry's reads (here one on the lane's
         // own tag, not settled)
         if constexpr (kSlots) claim(AB + me, 0);
-        while (cur != 0u || (kSlots && (pp || hq))) {
-          const bool live = !kSlots || (cur != 0u && !hq);
+        while (cur != 0u || (kSlots && pp)) {
+          const bool live = !kSlots || cur != 0u;
           const float4 e0 = n0, e1 = n1, e2 = n2, ej = nj, ep = np;
           const int cur_i = i;  // this entry's batch position
           {
@@ -774,40 +770,38 @@ __global__ __launch_bounds__(Shape<TILE>::NT, (MODE & 2) ? ((MODE & 4) ? 2 : 3) 
             // the step's arithmetic (which this empty statement consumes)
             asm volatile("" ::"v"(nva[0]), "v"(nva[1]), "v"(nva[2]), "v"(nva[3]), "v"(v4) : "memory");
             // settle the previous step's claim: the lane whose number stayed
-            // in the tag writes its sum back
+            // in the tag writes its sum back; then the lanes that lost add
+            // theirs with LDS atomics (after that write, in the LDS's order)
             const bool won = pp && rt == me;
             if (won) {
               *(f32x4 LDS_AS *)&accA[w][pidx] = ra + pva;
               *(AccB<kGeo> LDS_AS *)&accB[w][pidx] = rb + pvb;
             }
             kLdsOrder();
-            pp = pp && !won;
-            // what this step claims: a claim that lost, again (this step's
-            // values then wait, and the lane computes nothing next step); else
-            // the waiting values; else this step's
-            if (pp) {
-              if (real) {
-                hq = true;
-                qva = nva;
-                qvb = nvb;
-                qidx = cur_i;
+            if (pp && !won) {
+              float *fa = (float *)&accA[w][pidx];
+              float *fb = (float *)&accB[w][pidx];
+              atomicAdd(fa + 0, pva[0]);
+              atomicAdd(fa + 1, pva[1]);
+              atomicAdd(fa + 2, pva[2]);
+              atomicAdd(fa + 3, pva[3]);
+              if constexpr (kGeo) {
+#pragma unroll
+                for (int c = 0; c < 4; c++) atomicAdd(fb + c, pvb[c]);
+              } else {
+                atomicAdd(fb, pvb);
               }
-            } else if (hq) {
-              pp = true;
-              pva = qva;
-              pvb = qvb;
-              pidx = qidx;
-              hq = false;
-            } else if (real) {
-              pp = true;
-              pva = nva;
-              pvb = nvb;
-              pidx = cur_i;
             }
-            // every lane claims (a lane with nothing to claim its own tag), so
-            // that the LDS operations behind the next entry's reads are the
-            // same on every path and the next step waits for those reads only
-            claim(pp ? pidx : AB + me, pp ? pidx : cur_i);
+            kLdsOrder();
+            // this step's claim; every lane makes one (a lane with nothing to
+            // add on its own tag), so that the LDS operations behind the next
+            // entry's reads are the same on every path and the next step
+            // waits for those reads only
+            pp = ok && ep.w != 0.f;
+            pva = nva;
+            pvb = nvb;
+            pidx = cur_i;
+            claim(pp ? cur_i : AB + me, cur_i);
           }
         }
       }

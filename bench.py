@@ -571,6 +571,7 @@ def serving_run(seconds, rate, n_sections, budget_gib, seed=4, low_rate=0.0):
         return out
 
     # served form against one request per launch, on the same requests
+    log("bench: serving, %d queued requests batched vs one per launch" % args.serve_drain)
     drain(20, True); drain(5, False)   # warm both paths
     d_b, d_1 = drain(args.serve_drain, True), drain(args.serve_drain, False)
     served = dict(requests=d_b["requests"], batched_req_per_s=d_b["req_per_s"],
@@ -581,10 +582,14 @@ def serving_run(seconds, rate, n_sections, budget_gib, seed=4, low_rate=0.0):
     # sustainable rate: the highest offered rate whose p99 meets the objective
     sweep = []
     for r in args.serve_sweep:
+        log("bench: serving sweep, %g req/s for %g s" % (r, args.serve_sweep_seconds))
         o = run(r, seed + 11, False, args.serve_sweep_seconds)
         sweep.append(dict(offered=r, served=o["req_per_s"], p50_ms=o["p50_ms"], p99_ms=o["p99_ms"]))
     ok = [x["offered"] for x in sweep if x["p99_ms"] is not None and x["p99_ms"] <= args.serve_p99_ms]
+    if low_rate > 0:
+        log("bench: serving %g req/s for %g s" % (low_rate, seconds))
     low = run(low_rate, seed + 3, True) if low_rate > 0 else None
+    log("bench: serving %g req/s for %g s" % (rate, seconds))
     rep = run(rate, seed + 1, low is None)
     rep["served_vs_one_request_per_launch"] = served
     rep["rate_sweep"] = dict(p99_objective_ms=args.serve_p99_ms, seconds=args.serve_sweep_seconds,

@@ -667,11 +667,10 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, ui
 #pragma unroll
   for (int e = 0; e < E; e++) pad_tie |= l + kWave * e < n && (k[e] & nib) == nib;
   const unsigned long long diff = diff0 | (ballot64(pad_tie) != 0ull ? kTopNibble : 0ull);
-  if ((diff >> 32) == 0ull) {
-    // one depth for the whole tile: the order is the id order
-#pragma unroll
-    for (int e = 0; e < E; e++) buf[lds_pos(l * E + e)] = k[e];
-    wave_radix_passes<E>(k, diff & 0xFFFFFFFFull, buf, starts);
+  if ((diff0 >> 32) == 0ull) {
+    // one depth for the whole tile: the order is the id order, then the
+    // top depth nibble (below 8 in every real key) puts the padding last
+    wave_radix_passes<E>(k, (diff0 & 0xFFFFFFFFull) | kTopNibble, buf, starts);
   } else {
     wave_radix_passes<E>(k, diff & 0xFFFFFFFF00000000ull, buf, starts);
     // equal depths at consecutive positions?

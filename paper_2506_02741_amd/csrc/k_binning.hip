@@ -637,12 +637,13 @@ __device__ __forceinline__ void wave_radix_passes(unsigned long long (&k)[E], un
 }
 
 // Sort of one tile's n <= 64 * E keys (depth bits << 32 | id, unique) by a
-// one-wave block; the ids go to dst in ascending key order.  The keys are
+// one-wave block, written to dst in ascending key order as D (u32: the ids,
+// u64: the keys).  The keys are
 // loaded coalesced (any starting arrangement sorts to the same result, the
 // keys being unique).  Depth first, over the depth nibbles that vary; equal
 // depths (rare) are then put in id order as in the block sort.
-template <int E>
-__device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, uint32_t *dst, int n,
+template <int E, typename D>
+__device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, D *dst, int n,
                                unsigned long long *buf, uint32_t *starts) {
   const int l = lane_id();
   unsigned long long k[E];
@@ -725,7 +726,7 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, ui
       }
     }
   }
-  for (int i = l; i < n; i += kWave) dst[i] = (uint32_t)buf[lds_pos(i)];
+  for (int i = l; i < n; i += kWave) dst[i] = (D)buf[lds_pos(i)];
 }
 
 // One round of a merge sort over n keys held as sorted runs of `width`
@@ -833,38 +834,40 @@ __global__ __launch_bounds__(NT) void k_sort_tiles(Ws ws, int lo_n, int hi_n, in
     if (threadIdx.x == 0) dst[0] = (uint32_t)src[0];
     continue;
   }
-  if constexpr (kWaveSort) {
-    if (n <= NT * E1) wave_sort_tile<E1>(src, dst, n, buf, starts);
-    else if (n <= CAP) wave_sort_tile<E>(src, dst, n, buf, starts);
-  } else {
-    if (n <= NT * E1) sort_tile_regs<NT, E1>(src, dst, n, buf, wsum, red, starts);
-    else if (n <= NT * E2) sort_tile_regs<NT, E2>(src, dst, n, buf, wsum, red, starts);
-    else if (n <= CAP) sort_tile_regs<NT, E>(src, dst, n, buf, wsum, red, starts);
-    else {
-      // longer than the LDS holds: runs of CAP keys sorted in LDS into
-      // keys_tmp, then merged pairwise, back and forth between keys_tmp and
-      // the tile's own key range (free once its runs are sorted); the last
-      // round writes the ids
-      unsigned long long *runs = ws.keys_tmp + rg.x, *spare = ws.keys + rg.x;
-      for (int lo = 0; lo < n; lo += CAP) {
-        const int c = min(CAP, n - lo);
-        if (c <= NT * E1) sort_tile_regs<NT, E1>(src + lo, runs + lo, c, buf, wsum, red, starts);
-        else if (c <= NT * E2) sort_tile_regs<NT, E2>(src + lo, runs + lo, c, buf, wsum, red, starts);
-        else sort_tile_regs<NT, E>(src + lo, runs + lo, c, buf, wsum, red, starts);
-        __syncthreads();  // buf is reused by the next run
-      }
-      const unsigned long long *in = runs;
-      unsigned long long *out = spare;
-      int width = CAP;
-      for (; 2 * width < n; width *= 2) {
-        merge_round<NT>(in, out, n, width);
-        __syncthreads();
-        unsigned long long *nxt = const_cast<unsigned long long *>(in);
-        in = out;
-        out = nxt;
-      }
-      merge_round<NT>(in, dst, n, width);
+  // a list (or run) of c <= CAP keys sorted in LDS, written to d
+  auto sort_run = [&](const unsigned long long *s_, auto *d_, int c) {
+    if constexpr (kWaveSort) {
+      if (c <= NT * E1) wave_sort_tile<E1>(s_, d_, c, buf, starts);
+      else wave_sort_tile<E>(s_, d_, c, buf, starts);
+    } else {
+      if (c <= NT * E1) sort_tile_regs<NT, E1>(s_, d_, c, buf, wsum, red, starts);
+      else if (c <= NT * E2) sort_tile_regs<NT, E2>(s_, d_, c, buf, wsum, red, starts);
+      else sort_tile_regs<NT, E>(s_, d_, c, buf, wsum, red, starts);
     }
+  };
+  if (n <= CAP) {
+    sort_run(src, dst, n);
+  } else {
+    // longer than the LDS holds: runs of CAP keys sorted in LDS into
+    // keys_tmp, then merged pairwise, back and forth between keys_tmp and
+    // the tile's own key range (free once its runs are sorted); the last
+    // round writes the ids
+    unsigned long long *runs = ws.keys_tmp + rg.x, *spare = ws.keys + rg.x;
+    for (int lo = 0; lo < n; lo += CAP) {
+      sort_run(src + lo, runs + lo, min(CAP, n - lo));
+      __syncthreads();  // buf is reused by the next run
+    }
+    const unsigned long long *in = runs;
+    unsigned long long *out = spare;
+    int width = CAP;
+    for (; 2 * width < n; width *= 2) {
+      merge_round<NT>(in, out, n, width);
+      __syncthreads();
+      unsigned long long *nxt = const_cast<unsigned long long *>(in);
+      in = out;
+      out = nxt;
+    }
+    merge_round<NT>(in, dst, n, width);
   }
   __syncthreads();  // buf is reused by the block's next tile
   }
@@ -965,19 +968,22 @@ hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
 }
 
 hipError_t launch_sort_tiles(const Ws &ws, hipStream_t st) {
-  // one wave per tile: 4 or 12 keys per lane
-  hipLaunchKernelGGL((k_sort_tiles<kWave, kSmallSort / kWave>), dim3(ws.n_tiles), dim3(kWave), 0,
-                     st, ws, 0, kSmallSort, 0);
-  // lists longer than 768, queued by the scan, taken in turn by 512-thread
-  // blocks (6, 10 or 16 keys per thread): two per CU's worth of the grid
-  // when the records' expected pairs per tile (a Gaussian of extent ~4-5 px
+  // Where the records' expected pairs per tile (a Gaussian of extent ~4-5 px
   // covers about (1 + 10 / B)^2 tiles of side B) make long lists the rule,
-  // else a few blocks for the odd one (an empty queue ends them at once)
+  // lists of up to 768 go to one wave per tile (4 or 12 keys per lane) and
+  // the longer ones, queued by the scan, to 512-thread blocks taken in turn
+  // (6, 10 or 16 keys per thread; 8192 keys in LDS, longer lists merged from
+  // runs), a CU's worth of them.  Otherwise the one-wave blocks sort every
+  // list, a long one (the odd one) as runs of 768 merged in rounds, and no
+  // second kernel is launched.
   const double per = (1.0 + 10.0 / ws.tile) * (1.0 + 10.0 / ws.tile);
   const bool many = per * (double)ws.n_rec > 1024.0 * (double)ws.n_tiles;
-  const int nlong = std::min(ws.n_tiles, many ? 512 : 16);
-  hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(nlong), dim3(512), 0, st, ws,
-                     kSmallSort, 0x7fffffff, 1);
+  hipLaunchKernelGGL((k_sort_tiles<kWave, kSmallSort / kWave>), dim3(ws.n_tiles), dim3(kWave), 0,
+                     st, ws, 0, many ? kSmallSort : 0x7fffffff, 0);
+  if (many) {
+    hipLaunchKernelGGL((k_sort_tiles<512, kSortCap / 512>), dim3(std::min(ws.n_tiles, 512)), dim3(512),
+                       0, st, ws, kSmallSort, 0x7fffffff, 1);
+  }
   return hipGetLastError();
 }
 

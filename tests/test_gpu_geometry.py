@@ -159,3 +159,61 @@ def test_map_step_moves_depths_and_pose(R, orc):
     # the second keyframe keeps its depths and pose
     assert np.array_equal(np_(ks[1].depth), frames[1].depth.ravel())
     assert np.array_equal(np_(ks[1].pose), frames[1].pose.ravel())
+
+
+@pytest.mark.parametrize("geo", [False, True])
+def test_workspace_contents_never_read_before_written(R, geo):
+    """The same mapping backward in a workspace filled with 0xFF bytes and in
+    a zeroed one gives bitwise equal gradients: no kernel reads workspace
+    memory (lane bits, counters, scratch) that this plan has not written."""
+    import torch
+    cam, frames, vpose, ks = _section(R, 9, 96, 72, 3, geo=(geo, False, geo))
+    view = R.View(cam.as_tuple(), vpose, 0, 3)
+    probe = R.Plan(ks, [view], bind=False)
+    rng = np.random.default_rng(8)
+    g_rgb = T(rng.normal(size=(3, probe.P)))
+    out = []
+    for fill in (0xFF, 0x00):
+        ws = torch.full((probe.ws_bytes,), fill, dtype=torch.uint8, device="cuda")
+        plan = R.Plan(ks, [view], workspace=ws)
+        for k in ks:
+            k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+            if k.g_depth is not None:
+                k.g_depth.zero_(); k.g_pose.zero_()
+        imgs = [np_(x).copy() for x in plan.render_fwd()]
+        plan.render_bwd(g_rgb, None, None, twist=False)
+        assert plan.status()[0] == 0
+        out.append((imgs, [(np_(k.g_color).copy(), np_(k.g_opacity).copy(), np_(k.g_radius).copy())
+                           + ((np_(k.g_depth).copy(), np_(k.g_pose).copy()) if k.g_depth is not None else ())
+                           for k in ks]))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    for ga, gb in zip(out[0][1], out[1][1]):
+        for a, b in zip(ga, gb):
+            assert np.array_equal(a, b)
+
+
+def test_workspace_contents_never_read_before_written_tracking(R):
+    """Two tracking iterations of a two-view batch in a workspace filled with
+    0xFF bytes and in a zeroed one: bitwise equal poses and losses."""
+    import torch
+    from paper_2506_02741_amd import synth
+    ws_ = [synth.tracking_workload(s, 96, 72) for s in (1, 2)]
+    ks = [R.Keyframe.ingest(w["keyframe"].depth, w["keyframe"].rgb, w["keyframe"].cam.as_tuple(),
+                            w["keyframe"].pose) for w in ws_]
+
+    def views():
+        return [R.View(w["keyframe"].cam.as_tuple(), w["init_pose"], i, 1, w["keyframe"].rgb,
+                       w["keyframe"].depth).with_pose_adam() for i, w in enumerate(ws_)]
+    probe = R.Plan(ks, views(), bind=False)
+    out = []
+    for fill in (0xFF, 0x00):
+        vs = views()
+        ws = torch.full((probe.ws_bytes,), fill, dtype=torch.uint8, device="cuda")
+        plan = R.Plan(ks, vs, workspace=ws)
+        loss = plan.track_step(R.track_cfg(), iters=2)
+        assert plan.status()[0] == 0
+        out.append((np_(loss).copy(), [np_(v.pose).copy() for v in vs]))
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)

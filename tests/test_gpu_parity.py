@@ -498,6 +498,29 @@ def test_long_tile_lists_bitwise(R, orc, zoom, tile, n_kf):
     check_images(*imgs, oracle_ref(orc, ov, okfs, prm))
 
 
+@pytest.mark.parametrize("zoom", [4.0, 16.0])
+def test_odd_long_lists_in_a_sparse_plan_bitwise(R, orc, zoom):
+    """A 640x480 view (1,200 tiles) of one 96x72 keyframe seen from far away:
+    long lists are not the rule (6,912 records), so one wave per tile sorts
+    every list, the four long ones (2,668-3,117 entries at zoom 4, 5,149-5,892
+    at zoom 16) as runs of 768 merged in rounds."""
+    cam, frames, vpose = room_frames(9, 96, 72, n_kf=1)
+    ks = [gpu_kf(R, frames[0])]
+    c = (cam.fx / zoom, cam.fy / zoom, 320.0, 240.0, 640, 480)
+    plan = R.Plan(ks, [R.View(c, vpose, 0, 1)])
+    imgs = plan.render_fwd()
+    st = plan.debug_state()
+    assert plan.status()[0] == 0
+    okfs = [oracle_kf(orc, frames[0])]
+    ov = orc.ViewSpec(c, vpose, 0, 1)
+    keys, vals, ranges = orc.tile_lists(ov, okfs)
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert (lens > 768).sum() == 4 and lens.max() > 2600
+    assert same_ranges(np_(st["ranges"]), ranges)
+    assert np.array_equal(np_(st["ids"])[:len(vals)].astype(np.uint32), vals)
+    check_images(*imgs, oracle_ref(orc, ov, okfs))
+
+
 @pytest.mark.parametrize("case,tile", [("long_runs", 16), ("short_runs", 16), ("long_runs", 32)])
 def test_tile_lists_with_depth_ties(R, orc, case, tile):
     """Equal depths are ordered by id: a constant-depth back plane seen from

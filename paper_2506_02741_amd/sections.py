@@ -312,3 +312,68 @@ class SectionStore:
             ev.record(self._copy)
             return ev
         return None
+
+
+# -- checkpoint / resume ---------------------------------------------------------
+# The map is plain tensors: per keyframe its pixel indices, tied depths,
+# colour, opacity, radius, pose (and depth map), the learnable section's
+# optimiser states, and the sections' structure.  A checkpoint is one
+# safetensors file (tensors only, nothing executable) whose metadata holds
+# the structure as JSON.
+_KF_STATE = ("adam", "depth_adam", "pose_adam")
+
+
+def save_map(store: SectionStore, path):
+    """Write the store's sections (resident or offloaded) to `path`."""
+    import json
+    from safetensors.torch import save_file
+    tensors, sections = {}, []
+    for s in store.sections:
+        kfs = []
+        host = s.host if not s.resident else None
+        for j, k in enumerate(s.keyframes):
+            tag = "s%d.k%d." % (s.index, j)
+            for name in _KF_TENSORS + _KF_STATE:
+                t = host[j].get(name) if host is not None and name in _KF_TENSORS else getattr(k, name)
+                if t is not None:
+                    tensors[tag + name] = t.detach().to("cpu").contiguous()
+            c = k.cam
+            kfs.append(dict(cam=[c.fx, c.fy, c.cx, c.cy, c.width, c.height], learnable=k.learnable))
+        sections.append(dict(index=s.index, frozen=s.frozen, offloaded=not s.resident, keyframes=kfs))
+    meta = dict(sections=json.dumps(sections), total_gaussians=str(store.total_gaussians),
+                peak_resident=str(store.peak_resident))
+    save_file(tensors, str(path), metadata=meta)
+
+
+def load_map(path, device=None) -> SectionStore:
+    """A store rebuilt from `save_map`'s file: every section resident on
+    `device` (offloaded ones come back frozen), the learnable section with
+    its gradient buffers and optimiser states."""
+    import json
+    from safetensors import safe_open
+    dev = _dev(device)
+    store = SectionStore(dev)
+    with safe_open(str(path), framework="pt", device="cpu") as f:
+        meta = f.metadata()
+        names = set(f.keys())
+        for sd in json.loads(meta["sections"]):
+            kfs = []
+            for j, kd in enumerate(sd["keyframes"]):
+                tag = "s%d.k%d." % (sd["index"], j)
+                get = lambda n: f.get_tensor(tag + n).to(dev) if tag + n in names else None
+                k = Keyframe(tuple(kd["cam"]), get("pose"), get("pix"), get("depth"), get("color"),
+                             get("opacity"), get("radius"), learnable=kd["learnable"], device=dev)
+                k.depth_map = get("depth_map")
+                if k.learnable:
+                    k.with_grad_buffers()
+                    for n in _KF_STATE:
+                        setattr(k, n, get(n))
+                    if k.depth_adam is not None or k.pose_adam is not None:
+                        k.with_geometry_grads()
+                kfs.append(k)
+            s = Section(sd["index"], kfs)
+            s.frozen = bool(sd["frozen"])
+            store.sections.append(s)
+        store.total_gaussians = int(meta["total_gaussians"])
+        store.peak_resident = int(meta["peak_resident"])
+    return store

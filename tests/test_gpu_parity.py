@@ -428,6 +428,46 @@ def test_edge_cases(R, orc):
         check_images(*imgs, ref, max_marginal=1.0)
 
 
+def test_degenerate_views_backward_and_steps(R):
+    """Views with nothing to render: a view over no keyframes beside a normal
+    one (its twist is zero, the normal view's equals that view alone) and a
+    camera turned away from everything, tracked for two iterations (zero
+    loss, the pose unchanged bit for bit, no flags)."""
+    import torch
+    cam, frames, vpose = room_frames(5, 80, 60)
+    fr = frames[0]
+    k = gpu_kf(R, fr, learnable=True).with_grad_buffers()
+    views = [R.View(cam.as_tuple(), vpose, 0, 0), R.View(cam.as_tuple(), vpose, 0, 1)]
+    plan = R.Plan([k], views)
+    rgb, depth, sil = plan.render_fwd()
+    assert float(sil[:plan.offsets[1]].abs().max()) == 0.0
+    rng = np.random.default_rng(2)
+    g = T(rng.normal(size=(3, plan.P)))
+    tw = np_(plan.render_bwd(g, None, None))
+    assert plan.status()[0] == 0
+    assert not tw[0].any()
+    gc = np_(k.g_color).copy()
+    k.g_color.zero_(); k.g_opacity.zero_(); k.g_radius.zero_()
+    alone = R.Plan([k], [views[1]])
+    alone.render_fwd()
+    o = plan.offsets[1]
+    tw1 = np_(alone.render_bwd(g[:, o:o + alone.P].contiguous(), None, None))
+    assert np.array_equal(tw1[0], tw[1])
+    assert np.array_equal(np_(k.g_color), gc)
+    # a camera turned away from every Gaussian, tracked
+    back = fr.pose.copy()
+    back[:, :3] = -back[:, :3]
+    back[:, 3] = -back[:, 3]
+    kt = gpu_kf(R, fr)
+    v = R.View(cam.as_tuple(), back, 0, 1, fr.rgb, fr.depth).with_pose_adam()
+    p0 = np_(v.pose).copy()
+    tp = R.Plan([kt], [v])
+    loss = np_(tp.track_step(R.track_cfg(), iters=2))
+    assert tp.status()[0] == 0
+    assert not loss.any()
+    assert np.array_equal(np_(v.pose), p0)
+
+
 # ----------------------------------------------------------------------------
 # autograd wrapper
 # ----------------------------------------------------------------------------

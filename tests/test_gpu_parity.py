@@ -281,6 +281,51 @@ def test_backward_full_size_twist(R, orc):
     assert ok, (worst, np_(tw)[0], gref["twist"])
 
 
+# seed -> (width, height, keyframes, tile, batch): ragged tiles on both axes
+RANDOM_SCENES = {0: (88, 60, 1, 16, 256), 1: (72, 88, 2, 16, 256), 2: (104, 56, 3, 8, 128),
+                 3: (60, 100, 2, 32, 512), 4: (96, 72, 3, 16, 128), 5: (50, 66, 1, 8, 256)}
+
+
+@pytest.mark.parametrize("seed", sorted(RANDOM_SCENES))
+def test_random_attributes_forward_backward(R, orc, seed):
+    """Seeded scenes with random colours, opacities over (0.05, 1) -- so the
+    alpha_max clamp engages and its branch of dL/do is taken -- and radii
+    scaled 0.5-3x (longer, overlapping lists): images, per-Gaussian gradients
+    and the twist against the oracle at several tile/batch shapes."""
+    w, h, n_kf, tile, batch = RANDOM_SCENES[seed]
+    cam, frames, vpose = room_frames(100 + seed, w, h, n_kf=n_kf)
+    rng = np.random.default_rng(seed)
+    okfs, gks = [], []
+    for fr in frames:
+        base = oracle_kf(orc, fr)
+        n = base.n
+        color = rng.uniform(0.0, 1.0, (3, n)).astype(np.float32)
+        opa = rng.uniform(0.05, 1.0, n).astype(np.float32)
+        rad = (base.radius * rng.uniform(0.5, 3.0, n)).astype(np.float32)
+        okfs.append(orc.Keyframe(base.cam, base.pose, base.pix, base.depth, color, opa, rad))
+        gks.append(R.Keyframe(base.cam, base.pose, base.pix.astype(np.int64), base.depth, color, opa,
+                              rad, learnable=True).with_grad_buffers())
+    view = R.View(cam.as_tuple(), vpose, 0, n_kf)
+    plan = R.Plan(gks, [view], R.params(tile=tile, batch=batch))
+    imgs = plan.render_fwd()
+    assert plan.status()[0] == 0
+    ov = orc.ViewSpec(cam.as_tuple(), vpose, 0, n_kf)
+    ref = oracle_ref(orc, ov, okfs)
+    check_images(*imgs, ref, max_marginal=2e-3)
+    g_rgb, g_d, g_s = _random_upstream(plan.P, ref["marginal"], seed)
+    tw = plan.render_bwd(T(g_rgb), T(g_d), T(g_s))
+    gref = orc.render_bwd(ov, okfs, g_rgb, g_d, g_s)
+    off = 0
+    for k in gks:
+        for got, name in ((k.g_color, "color"), (k.g_opacity, "opacity"), (k.g_radius, "radius")):
+            ok, worst = grad_close(np_(got), gref[name][..., off:off + k.n], name,
+                                   gref["mag"][name][..., off:off + k.n])
+            assert ok, (name, worst)
+        off += k.n
+    ok, worst = grad_close(np_(tw)[0], gref["twist"], "twist", gref["mag"]["twist"])
+    assert ok, ("twist", worst, np_(tw)[0], gref["twist"])
+
+
 def test_backward_frozen_keyframe_gets_nothing(R, orc):
     cam, frames, vpose = room_frames(9, 64, 48, n_kf=2)
     a = gpu_kf(R, frames[0], learnable=True).with_grad_buffers()

@@ -108,7 +108,7 @@ struct vtgs_plan {
   bool any_geo = false;  // a learnable keyframe wants depth / pose gradients
   bool tile_order = false;  // composite the longest tile lists first
   // workspace layout
-  Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_rec_off, r_scan, r_tcount, r_tfill,
+  Region r_hdr, r_desc, r_recA, r_recB, r_rect, r_rec_cnt, r_zbits, r_rec_off, r_scan, r_tcount, r_tcount_ns, r_tfill, r_woff,
       r_ranges, r_long, r_order, r_keys, r_keys_tmp, r_ids, r_slots, r_kpose, r_bits, r_tfinal, r_last,
       r_img, r_gimg, r_twist, r_loss, r_ssim_map, r_ssim_part;
   int64_t desc_kf = 0, desc_view = 0, desc_seg = 0, desc_use_off = 0, desc_use = 0, desc_bytes = 0;
@@ -186,10 +186,13 @@ void layout(vtgs_plan *p) {
   take(p->r_recB, nr * 16);
   take(p->r_rect, nr * 8);
   take(p->r_rec_cnt, nr * 4);
+  take(p->r_zbits, nr * 4);
   take(p->r_rec_off, (nr + 1) * 4);
   take(p->r_scan, (rec_scan_blocks(nr) + 1) * 4);
   take(p->r_tcount, nt * 4);
+  take(p->r_tcount_ns, nt * 4);
   take(p->r_tfill, nt * 4);
+  take(p->r_woff, (nr + 63) / 64 * 64 * 4);
   take(p->r_ranges, nt * 8);
   take(p->r_long, nt * 4);
   take(p->r_order, nt * 4);
@@ -244,10 +247,13 @@ void make_ws(vtgs_plan *p) {
   w.recB = at<float4>(b, p->r_recB);
   w.rect = at<uint2>(b, p->r_rect);
   w.rec_cnt = at<uint32_t>(b, p->r_rec_cnt);
+  w.zbits = at<uint32_t>(b, p->r_zbits);
   w.rec_off = at<uint32_t>(b, p->r_rec_off);
   w.scan_part = at<uint32_t>(b, p->r_scan);
   w.tile_count = at<uint32_t>(b, p->r_tcount);
+  w.tile_count_ns = at<uint32_t>(b, p->r_tcount_ns);
   w.tile_fill = at<uint32_t>(b, p->r_tfill);
+  w.wave_off = at<uint32_t>(b, p->r_woff);
   w.ranges = at<uint2>(b, p->r_ranges);
   w.keys = at<unsigned long long>(b, p->r_keys);
   w.keys_tmp = at<unsigned long long>(b, p->r_keys_tmp);
@@ -416,6 +422,7 @@ int bind_to(vtgs_plan *p, char *ws, const char *h, hipStream_t st) {
   HIP_OK(launch_fill_u32((uint32_t *)(p->ws + p->r_hdr.off), 0u, 64, st));
   HIP_OK(launch_fill_u32(p->w.tile_count, 0u, p->n_tiles, st));
   HIP_OK(launch_fill_u32(p->w.tile_fill, 0u, p->n_tiles, st));
+  HIP_OK(launch_fill_u32(p->w.tile_count_ns, 0u, p->n_tiles, st));
   p->bound = true;
   p->fwd_done = false;
   p->slots_done = false;

@@ -5,7 +5,8 @@
 //             the keyframe pose (Sec. 3.2), move it to the view camera,
 //             project, Sigma_2D = r^2 J J^T + lowpass*I, conic, extent
 //             R = ceil(sqrt(q_cut * lambda_max)), tile rectangle; then count
-//             the Gaussian in each tile it covers (wave-aggregated atomics)
+//             the Gaussian in each tile it covers (wave-aggregated atomics,
+//             whose old values are the wave's positions in those tiles)
 //  scan_tiles exclusive scan of the tile counts -> per-tile [start, end)
 //  fill_keys  write (depth bits << 32 | view-local id) into the tile slots
 //  sort_tiles sort each tile's keys (ascending depth, ties by id) in LDS and
@@ -188,6 +189,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     if (!has) { x0 = 1; y0 = 0; x1 = 0; y1 = 0; }
     ws.rect[r] = make_uint2((uint32_t)x0 | ((uint32_t)y0 << 16), (uint32_t)x1 | ((uint32_t)y1 << 16));
     ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
+    // the depth again on its own, so that the key fill reads 4 B per record
+    ws.zbits[r] = __float_as_uint(pz);
   }
   const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
   if (box.shared) {
@@ -204,9 +207,13 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
       const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
       if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
     }
-    if (mine) atomicAdd(ws.tile_count + mt, mine);
+    // the atomic's old value is the group's first position in box tile j:
+    // kept for the key fill, which then claims nothing for this group
+    if (mine) ws.wave_off[(r & ~(kWave - 1)) + lane_id()] = atomicAdd(ws.tile_count + mt, mine);
   } else if (has) {
-    uint32_t *cnt = ws.tile_count + tile_base;
+    // the other groups' pairs take the positions after them, claimed by
+    // the key fill
+    uint32_t *cnt = ws.tile_count_ns + tile_base;
     for (int ty = y0; ty <= y1; ty++)
       for (int tx = x0; tx <= x1; tx++) atomicAdd(cnt + ty * tiles_x + tx, 1u);
   }
@@ -236,9 +243,10 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
   __syncthreads();
   for (int base = 0; base < ws.n_tiles; base += kScanNT * kScanPer) {
     const int i0 = base + threadIdx.x * kScanPer;
-    uint32_t v[kScanPer], sum = 0;
+    uint32_t v[kScanPer], vs[kScanPer], sum = 0;
     for (int k = 0; k < kScanPer; k++) {
-      v[k] = (i0 + k < ws.n_tiles) ? ws.tile_count[i0 + k] : 0u;
+      vs[k] = (i0 + k < ws.n_tiles) ? ws.tile_count[i0 + k] : 0u;
+      v[k] = vs[k] + ((i0 + k < ws.n_tiles) ? ws.tile_count_ns[i0 + k] : 0u);
       sum += v[k];
     }
     uint32_t tot;
@@ -253,7 +261,8 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
         ws.ranges[i] = make_uint2((uint32_t)s, (uint32_t)e);
         if (e - s > (unsigned long long)kSmallSort) ws.long_tiles[atomicAdd(&nlong_s, 1u)] = i;
         ws.tile_count[i] = 0;
-        ws.tile_fill[i] = 0;
+        ws.tile_count_ns[i] = 0;
+        ws.tile_fill[i] = vs[k];
       }
       pos += v[k];
     }
@@ -293,61 +302,95 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
   }
 }
 
+// Keys into tile slots.  A thread takes RPT records, r = (block * RPT + k) *
+// kNT + thread, so that each k is a group of 64 consecutive records, the
+// preprocess's wave; the loads of all k are issued first, then every
+// group's slot bases, then the key stores, so that a wave waits on one
+// round trip per phase rather than one per group (large plans; the tracking
+// frame, with ~5 waves per SIMD, takes one record per thread).  A group whose
+// rectangles share a tile box recomputes the preprocess's box and takes the
+// positions its atomics returned; the other groups claim positions after
+// all of those with atomics here.  Either way a tile's keys land in no fixed
+// order; the sort that follows fixes it.
+template <int RPT>
 __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
-  const int r = blockIdx.x * kNT + threadIdx.x;
-  const bool active = r < ws.n_rec;
-  bool has = false;
-  int view = 0, x0 = 1, y0 = 0, x1 = 0, y1 = 0, tiles_x = 1, tile_base = 0;
-  unsigned long long key = 0;
-  if (active) {
-    unpack_rect(ws.rect[r], x0, y0, x1, y1);
-    has = x0 <= x1;
-    view = find_view_by_record(ws, r);
-    const DevView &vw = ws.views[view];
-    tiles_x = vw.tiles_x;
-    tile_base = vw.tile_base;
-    const float z = ws.recA[3 * (int64_t)r + 1].z;
-    key = ((unsigned long long)__float_as_uint(z) << 32) | (uint32_t)(r - vw.rec_base);
+  bool has[RPT];
+  int x0[RPT], y0[RPT], x1[RPT], y1[RPT], tiles_x[RPT], tile_base[RPT], view[RPT];
+  unsigned long long key[RPT];
+  uint32_t zb[RPT];
+  uint2 rc[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; k++) {
+    const int r = (blockIdx.x * RPT + k) * kNT + threadIdx.x;
+    const int rr = min(r, ws.n_rec - 1);
+    rc[k] = ws.rect[rr];
+    zb[k] = ws.zbits[rr];
   }
-  const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
-  if (box.shared) {
-    // lane j claims the wave's slots in box tile j (all tiles in one round
-    // trip), then every tile's base is read from its owner lane (the tile
-    // index in the box's view, whatever lane j holds)
-    const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);
-    const int btb = __builtin_amdgcn_readlane(tile_base, box.src);
+#pragma unroll
+  for (int k = 0; k < RPT; k++) {
+    const int r = (blockIdx.x * RPT + k) * kNT + threadIdx.x;
+    const bool active = r < ws.n_rec;
+    unpack_rect(rc[k], x0[k], y0[k], x1[k], y1[k]);
+    has[k] = active && x0[k] <= x1[k];
+    if (!has[k]) { x0[k] = 1; y0[k] = 0; x1[k] = 0; y1[k] = 0; }
+    view[k] = active ? find_view_by_record(ws, r) : 0;
+    const DevView &vw = ws.views[view[k]];
+    tiles_x[k] = vw.tiles_x;
+    tile_base[k] = vw.tile_base;
+    key[k] = ((unsigned long long)zb[k] << 32) | (uint32_t)(r - vw.rec_base);
+  }
+  // claims: lane j claims the wave's slots in box tile j (all tiles of a
+  // group in one atomic instruction)
+  WaveBox box[RPT];
+  uint32_t base[RPT], lim[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; k++) {
+    box[k] = wave_box(has[k], view[k], x0[k], y0[k], x1[k], y1[k]);
+    base[k] = 0u; lim[k] = 0u;
+    if (!box[k].shared) continue;
+    const int btx = __builtin_amdgcn_readlane(tiles_x[k], box[k].src);
+    const int btb = __builtin_amdgcn_readlane(tile_base[k], box[k].src);
     uint32_t mine = 0u;
     int mt = 0;
-    for (int j = 0; j < box.area; j++) {
+    for (int j = 0; j < box[k].area; j++) {
       int tx, ty;
       bool in;
-      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
+      const unsigned long long m = box_ballot(box[k], j, has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
       if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
     }
-    uint32_t base = 0u, lim = 0u;
     if (mine) {
+      // the group's first position in the tile, claimed by the preprocess
       const uint2 rg = ws.ranges[mt];
-      base = rg.x + atomicAdd(ws.tile_fill + mt, mine);
-      lim = rg.y;
+      const int g0 = (blockIdx.x * RPT + k) * kNT + (threadIdx.x & ~(kWave - 1));
+      base[k] = rg.x + ws.wave_off[g0 + lane_id()];
+      lim[k] = rg.y;
     }
-    for (int j = 0; j < box.area; j++) {
-      int tx, ty;
-      bool in;
-      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
-      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base, j);
-      const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)lim, j);
-      if (in) {
-        const uint32_t pos = b + (uint32_t)__popcll(m & lanemask_lt());
-        if (pos < e) ws.keys[pos] = key;
+  }
+  // stores: every tile's base read from its owner lane (the tile index in
+  // the box's view, whatever lane j holds); groups without a shared box
+  // claim and store pair by pair
+#pragma unroll
+  for (int k = 0; k < RPT; k++) {
+    if (box[k].shared) {
+      for (int j = 0; j < box[k].area; j++) {
+        int tx, ty;
+        bool in;
+        const unsigned long long m = box_ballot(box[k], j, has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base[k], j);
+        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)lim[k], j);
+        if (in) {
+          const uint32_t pos = b + (uint32_t)__popcll(m & lanemask_lt());
+          if (pos < e) ws.keys[pos] = key[k];
+        }
       }
+    } else if (has[k]) {
+      for (int ty = y0[k]; ty <= y1[k]; ty++)
+        for (int tx = x0[k]; tx <= x1[k]; tx++) {
+          const int t = tile_base[k] + ty * tiles_x[k] + tx;
+          const uint32_t pos = ws.ranges[t].x + atomicAdd(ws.tile_fill + t, 1u);
+          if (pos < ws.ranges[t].y) ws.keys[pos] = key[k];
+        }
     }
-  } else if (has) {
-    for (int ty = y0; ty <= y1; ty++)
-      for (int tx = x0; tx <= x1; tx++) {
-        const int t = tile_base + ty * tiles_x + tx;
-        const uint32_t pos = ws.ranges[t].x + atomicAdd(ws.tile_fill + t, 1u);
-        if (pos < ws.ranges[t].y) ws.keys[pos] = key;
-      }
   }
 }
 
@@ -963,7 +1006,13 @@ hipError_t launch_scan_tiles(const Ws &ws, hipStream_t st) {
 
 hipError_t launch_fill_keys(const Ws &ws, hipStream_t st) {
   if (ws.n_rec == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_keys, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws);
+  // four records per thread once the grid holds several waves per SIMD
+  // at that rate (1,024 SIMDs)
+  if (ws.n_rec >= (1 << 20)) {
+    hipLaunchKernelGGL(k_fill_keys<4>, dim3(blocks_for(ws.n_rec, 4 * kNT)), dim3(kNT), 0, st, ws);
+  } else {
+    hipLaunchKernelGGL(k_fill_keys<1>, dim3(blocks_for(ws.n_rec, kNT)), dim3(kNT), 0, st, ws);
+  }
   return hipGetLastError();
 }
 

@@ -90,11 +90,15 @@ struct Ws {
   float4 *recB;                // [n_rec]: (px, py, learnable, 0)
   uint2 *rect;                 // [n_rec]: tx0|ty0<<16, tx1|ty1<<16 (tx0 > tx1: culled)
   uint32_t *rec_cnt;           // [n_rec] tiles per record
+  uint32_t *zbits;             // [n_rec] FP32 bits of the centre depth (the sort key's high word)
   uint32_t *rec_off;           // [n_rec + 1] exclusive scan of rec_cnt
   uint32_t *scan_part;         // [scan blocks + 1]
   // per tile
-  uint32_t *tile_count;        // [n_tiles]
-  uint32_t *tile_fill;         // [n_tiles]
+  uint32_t *tile_count;        // [n_tiles] pairs of record groups with a shared tile box
+  uint32_t *tile_count_ns;     // [n_tiles] pairs of the other groups
+  uint32_t *tile_fill;         // [n_tiles] next free list position of the other groups
+  uint32_t *wave_off;          // [n_rec rounded up to 64] per 64-record group, lane j: the
+                               // group's first position in its box tile j (relative)
   uint2 *ranges;               // [n_tiles] (start, end)
   // pairs
   unsigned long long *keys;    // [cap] (depth bits << 32) | view-local id

@@ -81,14 +81,34 @@ __device__ __forceinline__ WaveBox wave_box(bool has, int view, int x0, int y0, 
   return b;
 }
 
-// ballot of the lanes whose rectangle covers box tile j
-__device__ __forceinline__ unsigned long long box_ballot(const WaveBox &b, int j, bool has, int x0,
-                                                        int y0, int x1, int y1, int &tx, int &ty,
-                                                        bool &in) {
-  ty = b.by0 + j / b.nx;
-  tx = b.bx0 + j % b.nx;
+// Ballot of the lanes whose rectangle covers tile (tx, ty).
+__device__ __forceinline__ unsigned long long tile_ballot(bool has, int x0, int y0, int x1, int y1,
+                                                         int tx, int ty, bool &in) {
   in = has && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
   return ballot64(in);
+}
+
+// Box tiles in row-major order: (tx, ty) moves on to the next one.
+__device__ __forceinline__ void next_box_tile(const WaveBox &b, int &tx, int &ty) {
+  if (++tx == b.bx0 + b.nx) { tx = b.bx0; ty++; }
+}
+
+// Lane j of a shared box: the number of the wave's rectangles covering box
+// tile j (0 past the box) and that tile's index `mt` in the box's view
+// (tiles_x btx, first tile btb).
+__device__ __forceinline__ uint32_t box_counts(const WaveBox &b, bool has, int x0, int y0, int x1,
+                                               int y1, int btx, int btb, int &mt) {
+  uint32_t mine = 0u;
+  mt = 0;
+  const int me = lane_id();
+  int tx = b.bx0, ty = b.by0;
+  for (int j = 0; j < b.area; j++) {
+    bool in;
+    const uint32_t c = (uint32_t)__popcll(tile_ballot(has, x0, y0, x1, y1, tx, ty, in));
+    if (me == j) { mine = c; mt = btb + ty * btx + tx; }
+    next_box_tile(b, tx, ty);
+  }
+  return mine;
 }
 
 constexpr int kSegLds = 1024;  // segment starts the preprocess keeps in LDS
@@ -199,14 +219,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     // the tile index takes that view's geometry from a lane that does.
     const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);
     const int btb = __builtin_amdgcn_readlane(tile_base, box.src);
-    uint32_t mine = 0u;
-    int mt = 0;
-    for (int j = 0; j < box.area; j++) {
-      int tx, ty;
-      bool in;
-      const unsigned long long m = box_ballot(box, j, has, x0, y0, x1, y1, tx, ty, in);
-      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
-    }
+    int mt;
+    const uint32_t mine = box_counts(box, has, x0, y0, x1, y1, btx, btb, mt);
     // the atomic's old value is the group's first position in box tile j:
     // kept for the key fill, which then claims nothing for this group
     if (mine) ws.wave_off[(r & ~(kWave - 1)) + lane_id()] = atomicAdd(ws.tile_count + mt, mine);
@@ -350,14 +364,8 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     if (!box[k].shared) continue;
     const int btx = __builtin_amdgcn_readlane(tiles_x[k], box[k].src);
     const int btb = __builtin_amdgcn_readlane(tile_base[k], box[k].src);
-    uint32_t mine = 0u;
-    int mt = 0;
-    for (int j = 0; j < box[k].area; j++) {
-      int tx, ty;
-      bool in;
-      const unsigned long long m = box_ballot(box[k], j, has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
-      if (lane_id() == j) { mine = (uint32_t)__popcll(m); mt = btb + ty * btx + tx; }
-    }
+    int mt;
+    const uint32_t mine = box_counts(box[k], has[k], x0[k], y0[k], x1[k], y1[k], btx, btb, mt);
     if (mine) {
       // the group's first position in the tile, claimed by the preprocess
       const uint2 rg = ws.ranges[mt];
@@ -372,16 +380,17 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
 #pragma unroll
   for (int k = 0; k < RPT; k++) {
     if (box[k].shared) {
+      int tx = box[k].bx0, ty = box[k].by0;
       for (int j = 0; j < box[k].area; j++) {
-        int tx, ty;
         bool in;
-        const unsigned long long m = box_ballot(box[k], j, has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
+        const unsigned long long m = tile_ballot(has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
         const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base[k], j);
         const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)lim[k], j);
         if (in) {
           const uint32_t pos = b + (uint32_t)__popcll(m & lanemask_lt());
           if (pos < e) ws.keys[pos] = key[k];
         }
+        next_box_tile(box[k], tx, ty);
       }
     } else if (has[k]) {
       for (int ty = y0[k]; ty <= y1[k]; ty++)

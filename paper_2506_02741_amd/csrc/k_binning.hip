@@ -112,6 +112,7 @@ __device__ __forceinline__ uint32_t box_counts(const WaveBox &b, bool has, int x
 }
 
 constexpr int kSegLds = 1024;  // segment starts the preprocess keeps in LDS
+constexpr int kViewLds = 256;  // view descriptors the key fill keeps in LDS
 
 __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   const int r = blockIdx.x * kNT + threadIdx.x;
@@ -328,6 +329,11 @@ __global__ __launch_bounds__(kScanNT) void k_scan_tiles(Ws ws) {
 // order; the sort that follows fixes it.
 template <int RPT>
 __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
+  // the views' first records, tiles per row and first tiles, read by the
+  // block at once beside its records' loads and then searched in LDS
+  // (plans with more views search the descriptors in global memory)
+  __shared__ int3 vtab[kViewLds];
+  const bool view_lds = ws.n_views <= kViewLds;
   bool has[RPT];
   int x0[RPT], y0[RPT], x1[RPT], y1[RPT], tiles_x[RPT], tile_base[RPT], view[RPT];
   unsigned long long key[RPT];
@@ -340,6 +346,11 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     rc[k] = ws.rect[rr];
     zb[k] = ws.zbits[rr];
   }
+  if (view_lds) {
+    for (int v = threadIdx.x; v < ws.n_views; v += kNT)
+      vtab[v] = make_int3(ws.views[v].rec_base, ws.views[v].tiles_x, ws.views[v].tile_base);
+    __syncthreads();
+  }
 #pragma unroll
   for (int k = 0; k < RPT; k++) {
     const int r = (blockIdx.x * RPT + k) * kNT + threadIdx.x;
@@ -347,11 +358,22 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     unpack_rect(rc[k], x0[k], y0[k], x1[k], y1[k]);
     has[k] = active && x0[k] <= x1[k];
     if (!has[k]) { x0[k] = 1; y0[k] = 0; x1[k] = 0; y1[k] = 0; }
-    view[k] = active ? find_view_by_record(ws, r) : 0;
-    const DevView &vw = ws.views[view[k]];
-    tiles_x[k] = vw.tiles_x;
-    tile_base[k] = vw.tile_base;
-    key[k] = ((unsigned long long)zb[k] << 32) | (uint32_t)(r - vw.rec_base);
+    int rec_base;
+    if (view_lds) {
+      int lo = 0, hi = ws.n_views - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (vtab[mid].x <= r) lo = mid; else hi = mid - 1;
+      }
+      view[k] = active ? lo : 0;
+      const int3 e = vtab[view[k]];
+      rec_base = e.x; tiles_x[k] = e.y; tile_base[k] = e.z;
+    } else {
+      view[k] = active ? find_view_by_record(ws, r) : 0;
+      const DevView &vw = ws.views[view[k]];
+      rec_base = vw.rec_base; tiles_x[k] = vw.tiles_x; tile_base[k] = vw.tile_base;
+    }
+    key[k] = ((unsigned long long)zb[k] << 32) | (uint32_t)(r - rec_base);
   }
   // claims: lane j claims the wave's slots in box tile j (all tiles of a
   // group in one atomic instruction)

@@ -51,15 +51,15 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &x0, int &y0, int &x1,
   x0 = rc.x & 0xffff; y0 = rc.x >> 16; x1 = rc.y & 0xffff; y1 = rc.y >> 16;
 }
 
-// Tiles covered by a wave's rectangles.  When the whole wave belongs to one
-// view and its rectangles fit in a bounding box of at most 24 tiles, tile j
-// of that box (row-major) is owned by lane j: `own(j, t, count)` runs once
-// on every lane with the owner's tile and the number of lanes covering it
-// (count 0: no lane covers tile j), so one instruction can issue an atomic
-// per tile from all owners at once; `visit(j, t, m, in)` then runs for each
-// box tile on every lane with the ballot m of lanes covering it.  Otherwise
-// (mixed views or a large box) each lane visits its own tiles alone through
-// `single(t)`.
+constexpr int kBoxMax = 24;  // tiles of a shared box
+
+// Tiles covered by a wave's rectangles (a group of 64 consecutive records).
+// When the whole wave belongs to one view and its rectangles fit in a
+// bounding box of at most kBoxMax tiles, box tile j (row-major) is owned by
+// lane j: the lanes count their tiles in LDS counters, and lane j issues the
+// global atomic of tile j, so one instruction serves the whole box.
+// Otherwise (mixed views or a large box) each lane adds to its own tiles'
+// counters alone.
 struct WaveBox {
   int bx0, by0, nx, area;
   int src;  // a lane with a rectangle (when shared): its view is the box's
@@ -75,39 +75,41 @@ __device__ __forceinline__ WaveBox wave_box(bool has, int view, int x0, int y0, 
   const int bx1 = wave_max_i(has ? x1 : -1), by1 = wave_max_i(has ? y1 : -1);
   b.nx = bx1 - b.bx0 + 1;
   const long area = vmax < 0 ? 0 : (long)b.nx * (long)(by1 - b.by0 + 1);
-  b.shared = vmax >= 0 && vmin == vmax && area <= 24;
+  b.shared = vmax >= 0 && vmin == vmax && area <= kBoxMax;
   b.area = b.shared ? (int)area : 0;
   b.src = (int)__builtin_ctzll(ballot64(has) | (1ull << 63));
   return b;
 }
 
-// Ballot of the lanes whose rectangle covers tile (tx, ty).
-__device__ __forceinline__ unsigned long long tile_ballot(bool has, int x0, int y0, int x1, int y1,
-                                                         int tx, int ty, bool &in) {
-  in = has && tx >= x0 && tx <= x1 && ty >= y0 && ty <= y1;
-  return ballot64(in);
-}
+// An empty statement the compiler must take as reading and writing all
+// memory: LDS accesses keep their program order across it, and the LDS
+// executes a wave's accesses in that order.
+__device__ __forceinline__ void lds_order() { asm volatile("" ::: "memory"); }
 
-// Box tiles in row-major order: (tx, ty) moves on to the next one.
-__device__ __forceinline__ void next_box_tile(const WaveBox &b, int &tx, int &ty) {
-  if (++tx == b.bx0 + b.nx) { tx = b.bx0; ty++; }
+// Lane j's box tile (row-major in the box) as a tile index of the box's
+// view (tiles_x btx, first tile btb); lanes past the box get a tile of the
+// box's first row, unused.
+__device__ __forceinline__ int box_tile_of_lane(const WaveBox &b, int btx, int btb) {
+  const int j = lane_id(), nx = max(b.nx, 1);
+  const int q = j / nx;
+  return btb + (b.by0 + q) * btx + (b.bx0 + (j - q * nx));
 }
 
 // Lane j of a shared box: the number of the wave's rectangles covering box
-// tile j (0 past the box) and that tile's index `mt` in the box's view
-// (tiles_x btx, first tile btb).
+// tile j (0 past the box).  Every lane adds one to the counter of each box
+// tile its rectangle covers, in the wave's own LDS row `cnt` (kBoxMax).
 __device__ __forceinline__ uint32_t box_counts(const WaveBox &b, bool has, int x0, int y0, int x1,
-                                               int y1, int btx, int btb, int &mt) {
-  uint32_t mine = 0u;
-  mt = 0;
-  const int me = lane_id();
-  int tx = b.bx0, ty = b.by0;
-  for (int j = 0; j < b.area; j++) {
-    bool in;
-    const uint32_t c = (uint32_t)__popcll(tile_ballot(has, x0, y0, x1, y1, tx, ty, in));
-    if (me == j) { mine = c; mt = btb + ty * btx + tx; }
-    next_box_tile(b, tx, ty);
+                                               int y1, uint32_t *cnt) {
+  const int j = lane_id();
+  if (j < kBoxMax) cnt[j] = 0u;
+  lds_order();
+  if (has) {
+    for (int ty = y0; ty <= y1; ty++)
+      for (int tx = x0; tx <= x1; tx++) atomicAdd(&cnt[(ty - b.by0) * b.nx + (tx - b.bx0)], 1u);
   }
+  lds_order();
+  const uint32_t mine = j < b.area ? cnt[j] : 0u;
+  lds_order();
   return mine;
 }
 
@@ -119,6 +121,7 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   // the segments' first records, read by the block at once, then searched
   // in LDS (plans with more segments search them in global memory)
   __shared__ int seg_start[kSegLds];
+  __shared__ uint32_t box_cnt[kNT / kWave][kBoxMax];
   const bool seg_lds = ws.n_segs <= kSegLds;
   if (seg_lds) {
     for (int k = threadIdx.x; k < ws.n_segs; k += kNT) seg_start[k] = ws.segs[k].rec_start;
@@ -220,8 +223,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     // the tile index takes that view's geometry from a lane that does.
     const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);
     const int btb = __builtin_amdgcn_readlane(tile_base, box.src);
-    int mt;
-    const uint32_t mine = box_counts(box, has, x0, y0, x1, y1, btx, btb, mt);
+    const int mt = box_tile_of_lane(box, btx, btb);
+    const uint32_t mine = box_counts(box, has, x0, y0, x1, y1, box_cnt[threadIdx.x / kWave]);
     // the atomic's old value is the group's first position in box tile j:
     // kept for the key fill, which then claims nothing for this group
     if (mine) ws.wave_off[(r & ~(kWave - 1)) + lane_id()] = atomicAdd(ws.tile_count + mt, mine);
@@ -333,6 +336,8 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
   // block at once beside its records' loads and then searched in LDS
   // (plans with more views search the descriptors in global memory)
   __shared__ int3 vtab[kViewLds];
+  __shared__ uint32_t fill_cnt[kNT / kWave][kBoxMax], fill_base[kNT / kWave][kBoxMax],
+      fill_lim[kNT / kWave][kBoxMax];
   const bool view_lds = ws.n_views <= kViewLds;
   bool has[RPT];
   int x0[RPT], y0[RPT], x1[RPT], y1[RPT], tiles_x[RPT], tile_base[RPT], view[RPT];
@@ -375,8 +380,8 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     }
     key[k] = ((unsigned long long)zb[k] << 32) | (uint32_t)(r - rec_base);
   }
-  // claims: lane j claims the wave's slots in box tile j (all tiles of a
-  // group in one atomic instruction)
+  // lane j of a group with a shared box: box tile j's first position and
+  // end
   WaveBox box[RPT];
   uint32_t base[RPT], lim[RPT];
 #pragma unroll
@@ -386,34 +391,38 @@ __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
     if (!box[k].shared) continue;
     const int btx = __builtin_amdgcn_readlane(tiles_x[k], box[k].src);
     const int btb = __builtin_amdgcn_readlane(tile_base[k], box[k].src);
-    int mt;
-    const uint32_t mine = box_counts(box[k], has[k], x0[k], y0[k], x1[k], y1[k], btx, btb, mt);
-    if (mine) {
-      // the group's first position in the tile, claimed by the preprocess
-      const uint2 rg = ws.ranges[mt];
+    if (lane_id() < box[k].area) {
+      // the group's first position in box tile j, claimed by the
+      // preprocess (unused, and never written, where no rectangle of the
+      // group covers the tile)
+      const uint2 rg = ws.ranges[box_tile_of_lane(box[k], btx, btb)];
       const int g0 = (blockIdx.x * RPT + k) * kNT + (threadIdx.x & ~(kWave - 1));
       base[k] = rg.x + ws.wave_off[g0 + lane_id()];
       lim[k] = rg.y;
     }
   }
-  // stores: every tile's base read from its owner lane (the tile index in
-  // the box's view, whatever lane j holds); groups without a shared box
-  // claim and store pair by pair
+  // stores: lane j parks box tile j's first position and end in the wave's
+  // LDS row; every lane then takes a rank in each box tile its rectangle
+  // covers from that tile's LDS counter (in whatever order the lanes come:
+  // the sort fixes it).  Groups without a shared box claim and store pair
+  // by pair.
+  uint32_t *cnt = fill_cnt[threadIdx.x / kWave], *bs = fill_base[threadIdx.x / kWave],
+           *ls = fill_lim[threadIdx.x / kWave];
 #pragma unroll
   for (int k = 0; k < RPT; k++) {
     if (box[k].shared) {
-      int tx = box[k].bx0, ty = box[k].by0;
-      for (int j = 0; j < box[k].area; j++) {
-        bool in;
-        const unsigned long long m = tile_ballot(has[k], x0[k], y0[k], x1[k], y1[k], tx, ty, in);
-        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base[k], j);
-        const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)lim[k], j);
-        if (in) {
-          const uint32_t pos = b + (uint32_t)__popcll(m & lanemask_lt());
-          if (pos < e) ws.keys[pos] = key[k];
-        }
-        next_box_tile(box[k], tx, ty);
+      const int j = lane_id();
+      if (j < kBoxMax) { cnt[j] = 0u; bs[j] = base[k]; ls[j] = lim[k]; }
+      lds_order();
+      if (has[k]) {
+        for (int ty = y0[k]; ty <= y1[k]; ty++)
+          for (int tx = x0[k]; tx <= x1[k]; tx++) {
+            const int jj = (ty - box[k].by0) * box[k].nx + (tx - box[k].bx0);
+            const uint32_t pos = bs[jj] + atomicAdd(&cnt[jj], 1u);
+            if (pos < ls[jj]) ws.keys[pos] = key[k];
+          }
       }
+      lds_order();
     } else if (has[k]) {
       for (int ty = y0[k]; ty <= y1[k]; ty++)
         for (int tx = x0[k]; tx <= x1[k]; tx++) {

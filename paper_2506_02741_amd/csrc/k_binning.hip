@@ -113,6 +113,13 @@ __device__ __forceinline__ uint32_t box_counts(const WaveBox &b, bool has, int x
   return mine;
 }
 
+// A load through a descriptor's pointer, which addresses global memory:
+// read as such (the compiler cannot tell, and would issue a flat load).
+template <class T>
+__device__ __forceinline__ T gload(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+
 constexpr int kSegLds = 1024;  // segment starts the preprocess keeps in LDS
 constexpr int kViewLds = 256;  // view descriptors the key fill keeps in LDS
 
@@ -151,26 +158,29 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     // the descriptor fields used below, read up front (not inside branches)
     const float kfx = kf.fx, kfy = kf.fy, kcx = kf.cx, kcy = kf.cy;
     const float vfx = vw.fx, vfy = vw.fy, vcx = vw.cx, vcy = vw.cy;
-    const int kwidth = kf.width, vtiles_y = vw.tiles_y;
-    float M[12];
-    relative_pose(vw.pose, kf.pose, M);
+    const int kwidth = kf.width, vtiles_y = vw.tiles_y, kn = kf.n, klearn = kf.learnable;
+    const uint32_t *kpix = kf.pix;
+    const float *kdepth = kf.depth, *kradius = kf.radius, *kopa = kf.opacity, *kcolor = kf.color;
+    const float *vpose = vw.pose, *kpose = kf.pose;
     view = sg.view;
     tiles_x = vw.tiles_x;
     tile_base = vw.tile_base;
     const int i = r - sg.rec_start;
-    // the segment's relative pose, kept for the gradient gathers
-    if (i == 0) {
+    // the two poses and every per-Gaussian load issued together, before the
+    // arithmetic (and before any store, which the compiler could not move
+    // them past)
+    const uint32_t pix = gload(kpix, i);
+    const float d = gload(kdepth, i);
+    const float rad = gload(kradius, i);
+    const float o = gload(kopa, i);
+    const float c0 = gload(kcolor, i), c1 = gload(kcolor, (int64_t)kn + i),
+                c2 = gload(kcolor, 2 * (int64_t)kn + i);
+    float tv[12], tk[12];
 #pragma unroll
-      for (int c = 0; c < 12; c++) ws.segs[seg].M[c] = M[c];
-    }
-    // every per-Gaussian load issued together, before the arithmetic
-    const uint32_t pix = kf.pix[i];
-    const float d = kf.depth[i];
-    const float rad = kf.radius[i];
-    const float o = kf.opacity[i];
-    const float c0 = kf.color[i], c1 = kf.color[(int64_t)kf.n + i],
-                c2 = kf.color[2 * (int64_t)kf.n + i];
-    const float learn = kf.learnable ? 1.f : 0.f;
+    for (int c = 0; c < 12; c++) { tv[c] = gload(vpose, c); tk[c] = gload(kpose, c); }
+    float M[12];
+    relative_pose(tv, tk, M);
+    const float learn = klearn ? 1.f : 0.f;
     const int u = (int)(pix % (uint32_t)kwidth), v = (int)(pix / (uint32_t)kwidth);
     // back-projection of the tied depth pixel (keyframe camera), into the view
     float px, py, pz;
@@ -215,6 +225,11 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
     ws.rec_cnt[r] = has ? (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1)) : 0u;
     // the depth again on its own, so that the key fill reads 4 B per record
     ws.zbits[r] = __float_as_uint(pz);
+    // the segment's relative pose, kept for the gradient gathers
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < 12; c++) ws.segs[seg].M[c] = M[c];
+    }
   }
   const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
   if (box.shared) {

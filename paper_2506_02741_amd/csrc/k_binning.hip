@@ -727,10 +727,11 @@ __device__ __forceinline__ void wave_radix_passes(unsigned long long (&k)[E], un
       seen += 1ull << (4 * d);
       buf[lds_pos((int)min(pos, (uint32_t)(kWave * E - 1)))] = k[e];  // a permutation
     }
-    __syncthreads();
+    // one wave: its LDS accesses complete in program order, so no barrier
+    lds_order();
 #pragma unroll
     for (int e = 0; e < E; e++) k[e] = buf[lds_pos(l * E + e)];
-    __syncthreads();
+    lds_order();
   }
 }
 
@@ -820,7 +821,7 @@ __device__ __forceinline__ void wave_sort_tile(const unsigned long long *src, D 
       } else {
 #pragma unroll
         for (int e = 0; e < E; e++) buf[lds_pos(l * E + e)] = k[e];
-        __syncthreads();
+        lds_order();
       }
     }
   }

@@ -233,7 +233,8 @@ __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   }
   const WaveBox box = wave_box(has, view, x0, y0, x1, y1);
   if (box.shared) {
-    // lane j counts box tile j; one atomic instruction for the whole box.
+    // the lanes count their tiles in the wave's LDS row, then lane j adds
+    // box tile j's count with one atomic instruction for the whole box.
     // Lane j need not hold a record of the box's view (or any record), so
     // the tile index takes that view's geometry from a lane that does.
     const int btx = __builtin_amdgcn_readlane(tiles_x, box.src);

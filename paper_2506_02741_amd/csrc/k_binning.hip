@@ -126,10 +126,11 @@ constexpr int kViewLds = 256;  // view descriptors the key fill keeps in LDS
 __global__ __launch_bounds__(kNT) void k_preprocess(Ws ws) {
   const int r = blockIdx.x * kNT + threadIdx.x;
   // the segments' first records, read by the block at once, then searched
-  // in LDS (plans with more segments search them in global memory)
+  // in LDS (plans with more segments search them in global memory, plans
+  // with one take it without a search)
   __shared__ int seg_start[kSegLds];
   __shared__ uint32_t box_cnt[kNT / kWave][kBoxMax];
-  const bool seg_lds = ws.n_segs <= kSegLds;
+  const bool seg_lds = ws.n_segs > 1 && ws.n_segs <= kSegLds;
   if (seg_lds) {
     for (int k = threadIdx.x; k < ws.n_segs; k += kNT) seg_start[k] = ws.segs[k].rec_start;
     __syncthreads();
@@ -350,11 +351,12 @@ template <int RPT>
 __global__ __launch_bounds__(kNT) void k_fill_keys(Ws ws) {
   // the views' first records, tiles per row and first tiles, read by the
   // block at once beside its records' loads and then searched in LDS
-  // (plans with more views search the descriptors in global memory)
+  // (plans with more views search the descriptors in global memory, plans
+  // with one read its descriptor without a search)
   __shared__ int3 vtab[kViewLds];
   __shared__ uint32_t fill_cnt[kNT / kWave][kBoxMax], fill_base[kNT / kWave][kBoxMax],
       fill_lim[kNT / kWave][kBoxMax];
-  const bool view_lds = ws.n_views <= kViewLds;
+  const bool view_lds = ws.n_views > 1 && ws.n_views <= kViewLds;
   bool has[RPT];
   int x0[RPT], y0[RPT], x1[RPT], y1[RPT], tiles_x[RPT], tile_base[RPT], view[RPT];
   unsigned long long key[RPT];

@@ -377,6 +377,39 @@ def test_batched_views_equal_single(R, orc):
         assert np.allclose(np_(k.g_color), g, rtol=1e-5, atol=1e-7)
 
 
+def test_many_views_and_segments_equal_single(R, orc):
+    """300 small views over 4 keyframes in one plan: more views than the key
+    fill keeps in LDS and more (view, keyframe) segments than the
+    preprocess keeps in LDS, so both search their descriptors in global
+    memory.  Every view's images and tile lists equal those of the view
+    planned alone (bitwise), and a few views equal the oracle."""
+    from paper_2506_02741_amd import synth
+    cam, frames, vpose = room_frames(21, 40, 30, n_kf=4)
+    ks = [gpu_kf(R, fr) for fr in frames]
+    rng = np.random.default_rng(5)
+    vcam = synth.Camera(30.0, 30.0, 12.0, 9.0, 24, 18)
+    poses = [synth.perturb_pose(frames[i % 4].pose, rng, 0.05, 3.0).astype(np.float32)
+             for i in range(300)]
+    views = [R.View(vcam.as_tuple(), p, 0, 4) for p in poses]
+    batch = R.Plan(ks, views)
+    rgb, depth, sil = batch.render_fwd()
+    assert batch.status()[0] == 0
+    for v in range(0, 300, 7):
+        single = R.Plan(ks, [views[v]])
+        r1, d1, s1 = single.render_fwd()
+        o = batch.offsets[v]
+        sl = slice(o, o + single.P)
+        assert np.array_equal(np_(r1), np_(rgb)[:, sl]), v
+        assert np.array_equal(np_(d1), np_(depth)[sl]), v
+        assert np.array_equal(np_(s1), np_(sil)[sl]), v
+    okfs = [oracle_kf(orc, fr) for fr in frames]
+    for v in (0, 151, 299):
+        o = batch.offsets[v]
+        sl = slice(o, o + vcam.width * vcam.height)
+        ref = oracle_ref(orc, orc.ViewSpec(vcam.as_tuple(), poses[v], 0, 4), okfs)
+        check_images(np_(rgb)[:, sl], np_(depth)[sl], np_(sil)[sl], ref, max_marginal=1e-2)
+
+
 def test_uneven_resolutions_batch(R, orc):
     """Views of different sizes in one plan, each vs the oracle."""
     cam, frames, vpose = room_frames(9, 64, 48, n_kf=3)
